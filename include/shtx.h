@@ -1,0 +1,140 @@
+/*
+ * shtx — spherical-harmonic transforms of many scalar fields on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operation is the spectral-transform workload of the IFS that the paper
+ * optimises (Section 3, "Spectral Transform - Spherical Harmonics Dwarf";
+ * Section 2.2.2 names it the most important challenge of the IFS).  The
+ * paper gives no formula, so the definition implemented here is the
+ * textbook one, fixed below and mirrored by an independent FP64 CPU oracle:
+ *
+ *   inverse   g_{j,k} = sum_{m=0}^{M_j} c_m Re(F_m(mu_j) e^{i m lambda_k}),
+ *             F_m(mu_j) = sum_{n=m}^{N} a_n^m P̄_n^m(mu_j),
+ *             c_0 = 1, c_m = 2 (m >= 1), lambda_k = 2 pi k / nlon_j;
+ *   direct    a_n^m = (1/2) sum_{j: M_j >= m} w_j G_m(mu_j) P̄_n^m(mu_j),
+ *             G_m(mu_j) = (1/nlon_j) sum_k g_{j,k} e^{-i m lambda_k},
+ *             Im a_n^0 := 0;
+ *   adjoints  the transposes of both under the Euclidean inner product on
+ *             (Re, Im) of the stored triangle and on raw grid values.
+ *
+ * mu_j, w_j are the Gauss-Legendre nodes (descending, each the double nearest
+ * to the true root) and weights on nlat latitudes; P̄_n^m is normalised to
+ * (1/2) int_{-1}^{1} (P̄_n^m)^2 dmu = 1 with no Condon-Shortley phase;
+ * M_j = min(N, floor((nlon_j - 1)/2)) is the ring cutoff.  The octahedral grid
+ * O_{nlat/2} has 20 + 4 i points on the i-th ring from the nearer pole (the
+ * TCo grids the paper runs, Sections 3.1.4.1 and 3.2.2).
+ *
+ * Layouts (device memory, caller-owned, contiguous, 16-byte aligned):
+ *   spec  [nfld][nspec] interleaved complex, m-major, n ascending:
+ *         index(m, n) = m (2N + 3 - m) / 2 + (n - m); nspec = (N+1)(N+2)/2.
+ *         complex128 for SHTX_FP64 plans, complex64 otherwise.
+ *   grid  [nfld][npts] real, rings concatenated north to south, each ring
+ *         starting at lambda = 0.  float64 for SHTX_FP64 plans, float32
+ *         otherwise.
+ *
+ * Precision forms (the Legendre arithmetic; the ring FFTs run in the grid
+ * type): SHTX_FP64 plain double; SHTX_FP32 single precision on the matrix
+ * cores with FP32 accumulation; SHTX_BF16X3 split bfloat16 hi+lo operands
+ * (three products, lo*lo dropped) with per-m power-of-two scaling of the
+ * Legendre table and FP32 accumulation.
+ *
+ * Ownership and errors.  A plan owns its tables and workspace, allocated at
+ * create time and freed at destroy; the transform calls allocate nothing.
+ * Calls are asynchronous on the HIP stream passed (NULL = the default
+ * stream); a plan may be used from one stream at a time because its
+ * workspace is shared by every call.  Inputs are never modified; an output
+ * that overlaps an input is rejected.  Functions return SHTX_OK or a negative
+ * code; no C++ exception crosses this interface.  Device faults surface on
+ * the next synchronisation.
+ */
+#ifndef SHTX_H
+#define SHTX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct shtx_plan_s *shtx_plan;
+
+enum shtx_grid { SHTX_GRID_FULL = 0, SHTX_GRID_OCTAHEDRAL = 1 };
+enum shtx_prec { SHTX_FP64 = 0, SHTX_FP32 = 1, SHTX_BF16X3 = 2 };
+
+enum shtx_status {
+    SHTX_OK = 0,
+    SHTX_EINVAL = -1,      /* bad argument, null or overlapping pointers */
+    SHTX_ENOMEM = -2,      /* device or host allocation failed at plan time */
+    SHTX_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
+    SHTX_EUNSUPPORTED = -4 /* valid but unsupported (odd nlat, odd ring length) */
+};
+
+/* Flags for shtx_plan_create. */
+#define SHTX_FLAG_GRAPH 1u /* replay each transform as a captured hipGraph */
+
+typedef struct {
+    int32_t trunc, nlat, nfld, prec, grid;
+    int32_t max_nlon;
+    int64_t nspec;          /* complex coefficients per field */
+    int64_t npts;           /* grid points per field */
+    int64_t nfour;          /* kept Fourier coefficients per field: sum_j (M_j + 1) */
+    size_t table_bytes;     /* Legendre tables resident in HBM */
+    size_t workspace_bytes; /* Fourier workspace and FFT tables */
+    double legendre_flops;  /* algorithmic Legendre flops of one transform, all fields */
+    double plan_seconds;    /* wall time of shtx_plan_create */
+} shtx_info;
+
+/* Create a plan for triangular truncation `trunc` on `nlat` Gaussian
+ * latitudes (even).  grid = SHTX_GRID_FULL uses `nlon_full` (even) points on
+ * every ring; SHTX_GRID_OCTAHEDRAL ignores it.  `nfld` fields per call.
+ * Nodes, weights and P̄_n^m tables are generated on the device (FP64) on
+ * `hip_stream`; the call returns after they are complete. */
+int shtx_plan_create(shtx_plan *out, int trunc, int grid, int nlat, int nlon_full,
+                     int nfld, int prec, unsigned flags, void *hip_stream);
+
+int shtx_plan_info(shtx_plan p, shtx_info *out);
+
+/* Host copies of plan geometry: nlon[nlat] ring lengths. */
+int shtx_plan_ring_lengths(shtx_plan p, int32_t *nlon_host);
+
+/* Host copies of the device-generated Gauss nodes and weights, nlat each
+ * (descending mu). */
+int shtx_plan_nodes(shtx_plan p, double *mu_host, double *w_host);
+
+/* Host copy of the stored Legendre table for wavenumber m, unscaled to
+ * double: out[r][n - m] = P̄_n^m(mu_{j_m + r}) for the R_m northern rings
+ * carrying m (j_m = first such ring), n = m..trunc.  Returns R_m (>= 0) or an
+ * error.  out may be NULL to query R_m. */
+int shtx_plan_legendre(shtx_plan p, int m, double *out_host);
+
+/* Inverse transform spec -> grid. */
+int shtx_inv_trans(shtx_plan p, const void *spec_d, void *grid_d, void *hip_stream);
+/* Direct transform grid -> spec. */
+int shtx_dir_trans(shtx_plan p, const void *grid_d, void *spec_d, void *hip_stream);
+/* Adjoint of the inverse transform: grid -> spec. */
+int shtx_inv_trans_adj(shtx_plan p, const void *grid_d, void *spec_d, void *hip_stream);
+/* Adjoint of the direct transform: spec -> grid. */
+int shtx_dir_trans_adj(shtx_plan p, const void *spec_d, void *grid_d, void *hip_stream);
+
+/* Kernel timing.  With SHTX_FLAG_TIMING at plan creation every transform
+ * call records HIP events around each of its kernels on the call's stream.
+ * shtx_timing_read synchronises on the recorded events and returns, per
+ * kernel kind, the summed duration in milliseconds and the launch count:
+ * index 0 inverse-shaped Legendre GEMM (inv_trans, dir_trans_adj),
+ * 1 direct-shaped Legendre GEMM (dir_trans, inv_trans_adj), 2 ring c2r FFT,
+ * 3 ring r2c FFT.  Both arrays have 4 entries; either may be NULL.  At most
+ * 4096 launches are recorded between resets; later ones are not timed. */
+#define SHTX_FLAG_TIMING 2u
+int shtx_timing_reset(shtx_plan p);
+int shtx_timing_read(shtx_plan p, double *ms_sum, int32_t *count);
+
+int shtx_plan_destroy(shtx_plan p);
+
+const char *shtx_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SHTX_H */

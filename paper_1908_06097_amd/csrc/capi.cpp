@@ -1,0 +1,294 @@
+// C ABI of libshtx (declared in include/shtx.h).  Argument checking, the
+// order of kernel launches per transform, optional hipGraph replay and the
+// per-kernel timing events; the arithmetic lives in the kernels.
+#include <cstring>
+#include <new>
+
+#include "shtx_internal.h"
+
+namespace shtx {
+int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, int prec,
+               unsigned flags, hipStream_t stream);
+void free_plan(Plan &p);
+}  // namespace shtx
+
+struct shtx_plan_s {
+    shtx::Plan p;
+};
+
+using shtx::Plan;
+
+namespace {
+
+int hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return SHTX_OK;
+    (void)hipGetLastError();
+    return SHTX_EHIP;
+}
+
+size_t spec_bytes(const Plan &p) { return (size_t)p.nfld * p.nspec * (p.prec == SHTX_FP64 ? 16 : 8); }
+size_t grid_bytes(const Plan &p) { return (size_t)p.nfld * p.npts * (p.prec == SHTX_FP64 ? 8 : 4); }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+bool aligned16(const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; }
+
+// Launch the kernels of one transform kind on stream s.
+hipError_t launch_kind(Plan &p, int kind, const void *in, void *out, hipStream_t s, bool timed)
+{
+    hipError_t e = hipSuccess;
+    auto timed_launch = [&](int tkind, auto &&fn) -> hipError_t {
+        int slot = -1;
+        if (timed && p.n_timed < Plan::kMaxTimed) {
+            slot = p.n_timed++;
+            p.ev_kind[slot] = tkind;
+            hipError_t er = hipEventRecord(p.ev_start[slot], s);
+            if (er != hipSuccess) return er;
+        }
+        hipError_t r = fn();
+        if (r != hipSuccess) return r;
+        if (slot >= 0) return hipEventRecord(p.ev_stop[slot], s);
+        return hipSuccess;
+    };
+    switch (kind) {
+    case shtx::kInverse:
+        e = timed_launch(0, [&] { return shtx::launch_gemm_inverse(p, in, p.d_four, s); });
+        if (e == hipSuccess) e = timed_launch(2, [&] { return shtx::launch_fft_c2r(p, p.d_four, out, false, s); });
+        break;
+    case shtx::kDirectAdj:
+        e = timed_launch(0, [&] { return shtx::launch_gemm_inverse(p, in, p.d_four, s); });
+        if (e == hipSuccess) e = timed_launch(2, [&] { return shtx::launch_fft_c2r(p, p.d_four, out, true, s); });
+        break;
+    case shtx::kDirect:
+        e = timed_launch(3, [&] { return shtx::launch_fft_r2c(p, in, p.d_four, false, s); });
+        if (e == hipSuccess) e = timed_launch(1, [&] { return shtx::launch_gemm_direct(p, p.d_four, out, false, s); });
+        break;
+    case shtx::kInverseAdj:
+        e = timed_launch(3, [&] { return shtx::launch_fft_r2c(p, in, p.d_four, true, s); });
+        if (e == hipSuccess) e = timed_launch(1, [&] { return shtx::launch_gemm_direct(p, p.d_four, out, true, s); });
+        break;
+    default:
+        e = hipErrorInvalidValue;
+    }
+    return e;
+}
+
+int run(shtx_plan h, int kind, const void *in, void *out, void *stream)
+{
+    if (!h || !in || !out) return SHTX_EINVAL;
+    Plan &p = h->p;
+    bool spec_in = kind == shtx::kInverse || kind == shtx::kDirectAdj;
+    size_t nin = spec_in ? spec_bytes(p) : grid_bytes(p);
+    size_t nout = spec_in ? grid_bytes(p) : spec_bytes(p);
+    if (overlap(in, nin, out, nout)) return SHTX_EINVAL;
+    if (!aligned16(in) || !aligned16(out)) return SHTX_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    bool timed = (p.flags & SHTX_FLAG_TIMING) != 0;
+    bool graph = (p.flags & SHTX_FLAG_GRAPH) != 0 && !timed && s != nullptr;
+    if (!graph) return hip_status(launch_kind(p, kind, in, out, s, timed));
+
+    Plan::GraphEntry &g = p.graphs[kind];
+    if (!(g.exec && g.in == in && g.out == out && g.stream == s)) {
+        if (g.exec) {
+            (void)hipGraphExecDestroy(g.exec);
+            g.exec = nullptr;
+        }
+        hipGraph_t graph_obj = nullptr;
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_status(e);
+        hipError_t le = launch_kind(p, kind, in, out, s, false);
+        e = hipStreamEndCapture(s, &graph_obj);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (graph_obj) (void)hipGraphDestroy(graph_obj);
+            return hip_status(le != hipSuccess ? le : e);
+        }
+        e = hipGraphInstantiate(&g.exec, graph_obj, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph_obj);
+        if (e != hipSuccess) {
+            g.exec = nullptr;
+            return hip_status(e);
+        }
+        g.in = in;
+        g.out = out;
+        g.stream = s;
+    }
+    return hip_status(hipGraphLaunch(g.exec, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+int shtx_plan_create(shtx_plan *out, int trunc, int grid, int nlat, int nlon_full, int nfld,
+                     int prec, unsigned flags, void *hip_stream)
+{
+    if (!out) return SHTX_EINVAL;
+    *out = nullptr;
+    shtx_plan h = new (std::nothrow) shtx_plan_s;
+    if (!h) return SHTX_ENOMEM;
+    int rc = shtx::build_plan(h->p, trunc, grid, nlat, nlon_full, nfld, prec, flags,
+                              reinterpret_cast<hipStream_t>(hip_stream));
+    if (rc != SHTX_OK) {
+        shtx::free_plan(h->p);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return SHTX_OK;
+}
+
+int shtx_plan_info(shtx_plan h, shtx_info *o)
+{
+    if (!h || !o) return SHTX_EINVAL;
+    const Plan &p = h->p;
+    std::memset(o, 0, sizeof(*o));
+    o->trunc = p.trunc;
+    o->nlat = p.nlat;
+    o->nfld = p.nfld;
+    o->prec = p.prec;
+    o->grid = p.grid;
+    o->max_nlon = p.max_nlon;
+    o->nspec = p.nspec;
+    o->npts = p.npts;
+    o->nfour = p.nfour;
+    o->table_bytes = p.table_bytes;
+    o->workspace_bytes = p.workspace_bytes;
+    o->legendre_flops = p.legendre_flops;
+    o->plan_seconds = p.plan_seconds;
+    return SHTX_OK;
+}
+
+int shtx_plan_ring_lengths(shtx_plan h, int32_t *nlon)
+{
+    if (!h || !nlon) return SHTX_EINVAL;
+    std::memcpy(nlon, h->p.nlon.data(), sizeof(int32_t) * h->p.nlat);
+    return SHTX_OK;
+}
+
+int shtx_plan_nodes(shtx_plan h, double *mu, double *w)
+{
+    if (!h) return SHTX_EINVAL;
+    const Plan &p = h->p;
+    hipError_t e = hipSuccess;
+    if (mu) e = hipMemcpy(mu, p.d_mu, sizeof(double) * p.nlat, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && w) e = hipMemcpy(w, p.d_w, sizeof(double) * p.nlat, hipMemcpyDeviceToHost);
+    return hip_status(e);
+}
+
+int shtx_plan_legendre(shtx_plan h, int m, double *out)
+{
+    if (!h) return SHTX_EINVAL;
+    const Plan &p = h->p;
+    if (m < 0 || m > p.trunc) return SHTX_EINVAL;
+    const shtx::MBlock &b = p.mb[m];
+    if (!out) return b.R;
+    int K = p.trunc - m + 1;
+    size_t el = p.prec == SHTX_FP64 ? 8 : p.prec == SHTX_FP32 ? 4 : 2;
+    size_t cnt = 2 * (size_t)b.Rp * b.Kp;
+    std::vector<unsigned char> hi(cnt * el), lo;
+    hipError_t e = hipMemcpy(hi.data(), (const char *)p.d_tab_rk + b.off_rk * el, cnt * el,
+                             hipMemcpyDeviceToHost);
+    if (e == hipSuccess && p.prec == SHTX_BF16X3) {
+        lo.resize(cnt * el);
+        e = hipMemcpy(lo.data(), (const char *)p.d_tab_rk_lo + b.off_rk * el, cnt * el,
+                      hipMemcpyDeviceToHost);
+    }
+    if (e != hipSuccess) return hip_status(e);
+    auto val = [&](size_t idx) -> double {
+        if (p.prec == SHTX_FP64) return reinterpret_cast<const double *>(hi.data())[idx];
+        if (p.prec == SHTX_FP32) return reinterpret_cast<const float *>(hi.data())[idx];
+        auto bf = [](uint16_t u) {
+            uint32_t x = (uint32_t)u << 16;
+            float f;
+            std::memcpy(&f, &x, 4);
+            return (double)f;
+        };
+        double v = bf(reinterpret_cast<const uint16_t *>(hi.data())[idx]) +
+                   bf(reinterpret_cast<const uint16_t *>(lo.data())[idx]);
+        return std::ldexp(v, -b.e);
+    };
+    for (int r = 0; r < b.R; ++r)
+        for (int t = 0; t < K; ++t) {
+            int par = t & 1, k = t >> 1;
+            size_t idx = (size_t)par * b.Rp * b.Kp + (size_t)r * b.Kp + k;
+            out[(size_t)r * K + t] = val(idx);
+        }
+    return b.R;
+}
+
+int shtx_inv_trans(shtx_plan h, const void *spec, void *grid, void *stream)
+{
+    return run(h, shtx::kInverse, spec, grid, stream);
+}
+
+int shtx_dir_trans(shtx_plan h, const void *grid, void *spec, void *stream)
+{
+    return run(h, shtx::kDirect, grid, spec, stream);
+}
+
+int shtx_inv_trans_adj(shtx_plan h, const void *grid, void *spec, void *stream)
+{
+    return run(h, shtx::kInverseAdj, grid, spec, stream);
+}
+
+int shtx_dir_trans_adj(shtx_plan h, const void *spec, void *grid, void *stream)
+{
+    return run(h, shtx::kDirectAdj, spec, grid, stream);
+}
+
+int shtx_timing_reset(shtx_plan h)
+{
+    if (!h) return SHTX_EINVAL;
+    h->p.n_timed = 0;
+    return SHTX_OK;
+}
+
+int shtx_timing_read(shtx_plan h, double *ms_sum, int32_t *count)
+{
+    if (!h) return SHTX_EINVAL;
+    Plan &p = h->p;
+    double sum[4] = {0, 0, 0, 0};
+    int32_t cnt[4] = {0, 0, 0, 0};
+    for (int i = 0; i < p.n_timed; ++i) {
+        hipError_t e = hipEventSynchronize(p.ev_stop[i]);
+        if (e != hipSuccess) return hip_status(e);
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, p.ev_start[i], p.ev_stop[i]);
+        if (e != hipSuccess) return hip_status(e);
+        sum[p.ev_kind[i]] += ms;
+        cnt[p.ev_kind[i]] += 1;
+    }
+    for (int k = 0; k < 4; ++k) {
+        if (ms_sum) ms_sum[k] = sum[k];
+        if (count) count[k] = cnt[k];
+    }
+    return SHTX_OK;
+}
+
+int shtx_plan_destroy(shtx_plan h)
+{
+    if (!h) return SHTX_EINVAL;
+    (void)hipDeviceSynchronize();
+    shtx::free_plan(h->p);
+    delete h;
+    return SHTX_OK;
+}
+
+const char *shtx_strerror(int code)
+{
+    switch (code) {
+    case SHTX_OK: return "success";
+    case SHTX_EINVAL: return "invalid argument";
+    case SHTX_ENOMEM: return "out of memory";
+    case SHTX_EHIP: return "HIP runtime error";
+    case SHTX_EUNSUPPORTED: return "unsupported configuration";
+    default: return "unknown error";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,385 @@
+// Batched real FFTs along the latitude rings, one launch over every
+// (ring, run of fields).
+//
+// A real ring of n = 2h points goes through one complex DFT of length h
+// (even samples as real part, odd samples as imaginary part) with the usual
+// split/merge step around it.  The length-h DFT is a Stockham autosort
+// mixed-radix FFT (radices 8, 4, 2, 3, 5, 7) held in LDS, run in place: each
+// pass reads its butterflies into registers, synchronises, then writes.
+// Lengths with a prime factor above 7 go through Bluestein's chirp
+// convolution at a 7-smooth length L >= 2h - 1, with the filter spectrum
+// precomputed per ring length at plan time.  Only the kept wavenumbers
+// m <= M_j are read or written; they live in the Fourier workspace laid out
+// [ring][m][field], so a block's loads and stores are runs over fields.
+//
+// Inverse (c2r):  g_k = s_j * (Re Y_0 + 2 sum_{m=1}^{M} Re(Y_m e^{2 pi i m k / n}))
+//   transform:            Y_m = F_m,                    s_j = 1
+//   adjoint of direct:    Y_m = F_m / c_m,              s_j = w_j / (2 n)
+// Direct (r2c):   G_m = s_j fac_m sum_k g_k e^{-2 pi i m k / n},  m <= M
+//   transform:            fac_m = 1,    s_j = 1 / n
+//   adjoint of inverse:   fac_m = c_m,  s_j = 1
+//
+// The paper (Section 3.1.1) keeps fields resident on the device and packs on
+// the device; this kernel's layout and algorithm are this library's own.
+#include "shtx_internal.h"
+
+namespace shtx {
+
+namespace {
+
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) C2 {
+    T x, y;
+};
+
+template <typename T>
+__device__ inline C2<T> cmul(C2<T> a, C2<T> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ inline C2<T> cadd(C2<T> a, C2<T> b)
+{
+    return {a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ inline C2<T> csub(C2<T> a, C2<T> b)
+{
+    return {a.x - b.x, a.y - b.y};
+}
+template <typename T>
+__device__ inline C2<T> cconj(C2<T> a)
+{
+    return {a.x, -a.y};
+}
+// multiply by -i
+template <typename T>
+__device__ inline C2<T> cmi(C2<T> a)
+{
+    return {a.y, -a.x};
+}
+
+struct FftArgs {
+    const RingDesc *rings;
+    const FftItem *items;
+    const void *twid;
+    const void *in;
+    void *out;
+    int nfld;
+    int adjoint;
+    int64_t npts;
+};
+
+// Forward radix-R DFT of v in registers; wr[t] = exp(-2 pi i t / R).
+template <typename T, int R>
+__device__ inline void dft_reg(C2<T> *v, const C2<T> *wr)
+{
+    if constexpr (R == 2) {
+        C2<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else if constexpr (R == 4) {
+        C2<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        C2<T> s13 = cadd(v[1], v[3]), d13 = cmi(csub(v[1], v[3]));
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, d13);
+        v[3] = csub(d02, d13);
+    } else if constexpr (R == 8) {
+        // two radix-4 DFTs (even and odd samples) merged with exp(-2 pi i k / 8)
+        C2<T> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        dft_reg<T, 4>(e, wr);
+        dft_reg<T, 4>(o, wr);
+        const T c = T(0.70710678118654752440084436210484903928);
+        C2<T> o1 = {c * (o[1].x + o[1].y), c * (o[1].y - o[1].x)};   // * (1 - i)/sqrt2
+        C2<T> o2 = cmi(o[2]);                                           // * -i
+        C2<T> o3 = {c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y)};   // * (-1 - i)/sqrt2
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], o1);
+        v[5] = csub(e[1], o1);
+        v[2] = cadd(e[2], o2);
+        v[6] = csub(e[2], o2);
+        v[3] = cadd(e[3], o3);
+        v[7] = csub(e[3], o3);
+    } else {
+        // odd R: pair r with R - r
+        constexpr int H = (R - 1) / 2;
+        C2<T> sum[H], dif[H];
+#pragma unroll
+        for (int r = 1; r <= H; ++r) {
+            sum[r - 1] = cadd(v[r], v[R - r]);
+            dif[r - 1] = csub(v[r], v[R - r]);
+        }
+        C2<T> x0 = v[0];
+        C2<T> out0 = x0;
+#pragma unroll
+        for (int r = 0; r < H; ++r) out0 = cadd(out0, sum[r]);
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            C2<T> re = x0, im = {T(0), T(0)};
+#pragma unroll
+            for (int r = 1; r <= H; ++r) {
+                C2<T> w = wr[(k * r) % R];  // (cos, -sin) of 2 pi k r / R
+                re.x += sum[r - 1].x * w.x;
+                re.y += sum[r - 1].y * w.x;
+                im.x += dif[r - 1].x * w.y;
+                im.y += dif[r - 1].y * w.y;
+            }
+            // X_k = re + i*im', X_{R-k} = re - i*im' with im' = -sum dif sin
+            v[k] = {re.x - im.y, re.y + im.x};
+            v[R - k] = {re.x + im.y, re.y - im.x};
+        }
+        v[0] = out0;
+    }
+}
+
+// One in-place Stockham pass of radix R over nf fields of length L in LDS.
+template <typename T, int R, int CAP>
+__device__ void stockham_pass(C2<T> *buf, int lbuf, int nf, int L, int Ns, const C2<T> *W)
+{
+    constexpr int NB = (CAP / R + kFftThreads - 1) / kFftThreads;
+    const int nbf = L / R, total = nf * nbf;
+    const int tstep = L / (Ns * R);
+    C2<T> v[NB][R];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        int e = threadIdx.x + b * kFftThreads;
+        if (e < total) {
+            int f = e / nbf, j = e - f * nbf;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b][r] = buf[f * lbuf + j + r * nbf];
+        }
+    }
+    __syncthreads();
+    C2<T> wr[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) wr[t] = W[t * (L / R)];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        int e = threadIdx.x + b * kFftThreads;
+        if (e < total) {
+            int f = e / nbf, j = e - f * nbf;
+            int k = j % Ns;
+#pragma unroll
+            for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], W[k * r * tstep]);
+            dft_reg<T, R>(v[b], wr);
+            int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[f * lbuf + base + r * Ns] = v[b][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int CAP>
+__device__ void fft_forward(C2<T> *buf, const RingDesc &d, int nf, const C2<T> *W)
+{
+    int Ns = 1;
+    for (int s = 0; s < d.nrad; ++s) {
+        int R = d.rad[s];
+        switch (R) {
+        case 2: stockham_pass<T, 2, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
+        case 3: stockham_pass<T, 3, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
+        case 4: stockham_pass<T, 4, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
+        case 5: stockham_pass<T, 5, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
+        case 7: stockham_pass<T, 7, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
+        default: stockham_pass<T, 8, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
+        }
+        Ns *= R;
+    }
+}
+
+// Length-h forward DFT of the h values at the start of each field slot.
+// Plain: a Stockham FFT of length h.  Bluestein: the input must already be
+// multiplied by the chirp and zero-padded to L; the result is left as
+// conj(conv) and the caller multiplies by the chirp when reading (see
+// dft_out below).
+template <typename T, int CAP>
+__device__ void dft_h(C2<T> *buf, const RingDesc &d, int nf, const C2<T> *W, const C2<T> *bhat)
+{
+    fft_forward<T, CAP>(buf, d, nf, W);
+    if (d.blue) {
+        for (int e = threadIdx.x; e < nf * d.L; e += kFftThreads) {
+            int f = e / d.L, k = e - f * d.L;
+            C2<T> *q = buf + f * d.lbuf + k;
+            *q = cconj(cmul(*q, bhat[k]));
+        }
+        __syncthreads();
+        fft_forward<T, CAP>(buf, d, nf, W);
+    }
+}
+
+template <typename T>
+__device__ inline C2<T> dft_out(const C2<T> *slot, const RingDesc &d, const C2<T> *chirp, int k)
+{
+    return d.blue ? cmul(chirp[k], cconj(slot[k])) : slot[k];
+}
+
+template <typename T, int CAP>
+__global__ __launch_bounds__(kFftThreads) void k_fft_c2r(FftArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const FftItem it = a.items[item];
+    if (it.ring < 0) return;
+    const RingDesc d = a.rings[it.ring];
+    const C2<T> *tw = (const C2<T> *)a.twid;
+    const C2<T> *W = tw + d.tw_off, *post = tw + d.post_off;
+    const C2<T> *chirp = tw + d.chirp_off, *bhat = tw + d.bhat_off;
+    const int nf = it.nf, f0 = it.f0, h = d.h, M = d.M, lbuf = d.lbuf;
+    const C2<T> *four = (const C2<T> *)a.in + d.four_off;
+    const T facpos = a.adjoint ? T(0.5) : T(1);
+
+    // 1. kept coefficients Y_m (m <= M), zero up to index h (and to L for Bluestein)
+    const int span = d.blue ? d.L : h + 1;
+    for (int e = threadIdx.x; e < nf * span; e += kFftThreads) {
+        int m = e / nf, f = e - m * nf;
+        C2<T> y = {T(0), T(0)};
+        if (m <= M) {
+            y = four[(int64_t)m * a.nfld + f0 + f];
+            if (m == 0)
+                y.y = T(0);
+            else
+                y = {y.x * facpos, y.y * facpos};
+        }
+        buf[f * lbuf + m] = y;
+    }
+    __syncthreads();
+    // 2. merge into the length-h sequence u = conj(Z'), Z'_m = (Y_m + conj Y_{h-m})
+    //    + i e^{2 pi i m / n} (Y_m - conj Y_{h-m}); Bluestein: times the chirp
+    const int hp = h / 2 + 1;
+    for (int e = threadIdx.x; e < nf * hp; e += kFftThreads) {
+        int f = e / hp, m = e - f * hp;
+        C2<T> *s = buf + f * lbuf;
+        C2<T> ym = s[m], yh = s[h - m];
+        auto zprime = [&](C2<T> a1, C2<T> a2, int mm) {
+            C2<T> A = cadd(a1, cconj(a2)), B = csub(a1, cconj(a2));
+            C2<T> t = cmul(cconj(post[mm]), B);
+            C2<T> z = {A.x - t.y, A.y + t.x};
+            C2<T> u = cconj(z);
+            return d.blue ? cmul(u, chirp[mm]) : u;
+        };
+        C2<T> um = zprime(ym, yh, m);
+        if (m != 0 && m != h - m) s[h - m] = zprime(yh, ym, h - m);
+        s[m] = um;
+    }
+    __syncthreads();
+    // 3. forward DFT of length h
+    dft_h<T, CAP>(buf, d, nf, W, bhat);
+    // 4. z = conj(DFT(u)): even samples Re z, odd samples Im z
+    const T scale = a.adjoint ? T(d.w / (2.0 * d.n)) : T(1);
+    T *grid = (T *)a.out;
+    for (int e = threadIdx.x; e < nf * h; e += kFftThreads) {
+        int f = e / h, k = e - f * h;
+        C2<T> r = dft_out(buf + f * lbuf, d, chirp, k);
+        C2<T> g = {scale * r.x, -scale * r.y};
+        *reinterpret_cast<C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k) = g;
+    }
+}
+
+template <typename T, int CAP>
+__global__ __launch_bounds__(kFftThreads) void k_fft_r2c(FftArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const FftItem it = a.items[item];
+    if (it.ring < 0) return;
+    const RingDesc d = a.rings[it.ring];
+    const C2<T> *tw = (const C2<T> *)a.twid;
+    const C2<T> *W = tw + d.tw_off, *post = tw + d.post_off;
+    const C2<T> *chirp = tw + d.chirp_off, *bhat = tw + d.bhat_off;
+    const int nf = it.nf, f0 = it.f0, h = d.h, M = d.M, lbuf = d.lbuf;
+    const T *grid = (const T *)a.in;
+
+    // 1. z_k = g_{2k} + i g_{2k+1}; Bluestein: times the chirp, zero-padded to L
+    const int span = d.blue ? d.L : h;
+    for (int e = threadIdx.x; e < nf * span; e += kFftThreads) {
+        int f = e / span, k = e - f * span;
+        C2<T> z = {T(0), T(0)};
+        if (k < h) {
+            z = *reinterpret_cast<const C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k);
+            if (d.blue) z = cmul(z, chirp[k]);
+        }
+        buf[f * lbuf + k] = z;
+    }
+    __syncthreads();
+    dft_h<T, CAP>(buf, d, nf, W, bhat);
+    // 3. split: Y_m = (Z_m + conj Z_{h-m}) / 2 - (i/2) e^{-2 pi i m / n} (Z_m - conj Z_{h-m})
+    const T scale = a.adjoint ? T(1) : T(1.0 / d.n);
+    C2<T> *four = (C2<T> *)a.out + d.four_off;
+    for (int e = threadIdx.x; e < nf * (M + 1); e += kFftThreads) {
+        int m = e / nf, f = e - m * nf;
+        const C2<T> *s = buf + f * lbuf;
+        C2<T> zm = dft_out(s, d, chirp, m);
+        C2<T> zc = cconj(dft_out(s, d, chirp, m == 0 ? 0 : h - m));
+        C2<T> A = cadd(zm, zc), B = csub(zm, zc);
+        C2<T> t = cmul(post[m], B);
+        C2<T> y = {T(0.5) * (A.x + t.y), T(0.5) * (A.y - t.x)};
+        T fac = (a.adjoint && m > 0) ? T(2) : T(1);
+        y = {y.x * scale * fac, m == 0 ? T(0) : y.y * scale * fac};
+        four[(int64_t)m * a.nfld + f0 + f] = y;
+    }
+}
+
+template <typename T>
+bool check_fft(const Plan &p, int cap)
+{
+    if (p.fft_items.empty() || p.fft_items.size() % kXcds) return false;
+    size_t celem = 2 * sizeof(T);
+    for (const RingDesc &d : p.rings) {
+        if (d.lbuf > cap || d.L > d.lbuf || d.h + 1 > d.lbuf || d.M >= d.h) return false;
+        if ((size_t)d.fb * d.lbuf * celem > (size_t)p.fft_lds_bytes) return false;
+        if (d.tw_off < 0 || d.tw_off + d.L > p.twid_elems) return false;
+        if (d.post_off < 0 || d.post_off + d.h + 1 > p.twid_elems) return false;
+        if (d.blue && (d.chirp_off < 0 || d.chirp_off + d.h > p.twid_elems || d.bhat_off < 0 ||
+                       d.bhat_off + d.L > p.twid_elems))
+            return false;
+        if (d.grid_off + d.n > p.npts || d.four_off + (int64_t)(d.M + 1) * p.nfld > p.nfour * p.nfld)
+            return false;
+        int prod = 1;
+        for (int s = 0; s < d.nrad; ++s) prod *= d.rad[s];
+        if (prod != d.L) return false;
+    }
+    for (const FftItem &it : p.fft_items) {
+        if (it.ring < 0) continue;
+        if (it.ring >= p.nlat || it.f0 < 0 || it.nf < 1 || it.f0 + it.nf > p.nfld) return false;
+        if (it.nf > p.rings[it.ring].fb) return false;
+    }
+    return true;
+}
+
+template <typename T, int CAP, bool C2R>
+hipError_t launch_fft(const Plan &p, const void *in, void *out, bool adjoint, hipStream_t s)
+{
+    if (!check_fft<T>(p, CAP)) return hipErrorInvalidValue;
+    FftArgs a{p.d_rings, p.d_fft_items, p.d_twid, in, out, p.nfld, adjoint ? 1 : 0, p.npts};
+    auto kern = C2R ? k_fft_c2r<T, CAP> : k_fft_r2c<T, CAP>;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, CAP * (int)sizeof(C2<T>));
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    kern<<<(int)p.fft_items.size(), kFftThreads, p.fft_lds_bytes, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fft_c2r(const Plan &p, const void *four, void *grid, bool adjoint, hipStream_t s)
+{
+    if (p.prec == SHTX_FP64) return launch_fft<double, kFftCapF64, true>(p, four, grid, adjoint, s);
+    return launch_fft<float, kFftCapF32, true>(p, four, grid, adjoint, s);
+}
+
+hipError_t launch_fft_r2c(const Plan &p, const void *grid, void *four, bool adjoint, hipStream_t s)
+{
+    if (p.prec == SHTX_FP64) return launch_fft<double, kFftCapF64, false>(p, grid, four, adjoint, s);
+    return launch_fft<float, kFftCapF32, false>(p, grid, four, adjoint, s);
+}
+
+}  // namespace shtx

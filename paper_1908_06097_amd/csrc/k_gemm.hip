@@ -1,0 +1,509 @@
+// Legendre transforms as grouped, even/odd-split GEMMs on the CDNA4 matrix
+// cores, one launch per direction covering every wavenumber m.
+//
+// For each m the n-range splits by the parity p of n - m, and the equatorial
+// symmetry P̄_n^m(-mu) = (-1)^(n-m) P̄_n^m(mu) lets one product over the
+// northern rings serve both hemispheres:
+//
+//   inverse:  S_p[r][c] = sum_k P_p[r][k] B_p[k][c],   B_p[k][c] = a^m_{m+p+2k}
+//             F_m(north r) = S_0 + S_1,  F_m(south r) = S_0 - S_1
+//   direct:   D_p[k][c] = sum_r P_p[r][k] A_p[r][c],
+//             A_p[r][c] = q_r (G_m(north r) + (-1)^p G_m(south r))
+//
+// with c running over (field, re/im) pairs (the table is real), r over the
+// R_m northern rings carrying m and q_r = w_r / 2 (direct transform) or 1
+// (adjoint of the inverse).  The spectral operand is read from / written to
+// the caller's [field][nspec] array directly (the pack and unpack steps are
+// fused into the tile loads and the epilogue), and the Fourier operand lives
+// in the [ring][m][field] workspace that the ring FFTs read and write.
+//
+// The paper treats this step only as part of the SH dwarf (Section 3.1.1);
+// the design (grouped launch, XCD-aware work lists, LDS-staged tiles, MFMA)
+// is this library's own.
+#include "shtx_internal.h"
+
+namespace shtx {
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+template <typename T>
+struct Acc;
+template <>
+struct Acc<float> {
+    typedef f32x4 type;
+};
+template <>
+struct Acc<double> {
+    typedef f64x4 type;
+};
+
+// 16x16x4 MFMA: lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
+// D[4(l/16)+v][l%16] for v = 0..3.
+__device__ inline f32x4 mfma16x16x4(float a, float b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline f64x4 mfma16x16x4(double a, double b, f64x4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+struct GemmArgs {
+    const void *tab;     // table for the A operand
+    const void *tab_lo;  // split-BF16 lo half of the table
+    const MBlock *mb;
+    const GemmItem *items;
+    const RingDesc *rings;
+    const void *in;
+    void *out;
+    int trunc, nlat, nfld;
+    int adjoint;
+    int64_t nspec;
+};
+
+__device__ inline int64_t spec_base(int trunc, int m) { return (int64_t)m * (2 * trunc + 3 - m) / 2; }
+
+// ---------------------------------------------------------------------------
+// FP64 / FP32: 2 x 2 waves, each owning a (BM/2) x (BN/2) tile per parity.
+// LDS tiles are K-major: As[p][kappa][i], Bs[p][kappa][j].
+// ---------------------------------------------------------------------------
+template <typename T, int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void k_leg_inv_mfma(GemmArgs a)
+{
+    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+    constexpr int LDA = BM + 4, LDB = BN + 4;
+    typedef typename Acc<T>::type V;
+    __shared__ T As[2][BK][LDA];
+    __shared__ T Bs[2][BK][LDB];
+
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const GemmItem it = a.items[item];
+    if (it.m < 0) return;
+    const int m = it.m;
+    const MBlock b = a.mb[m];
+    const int row0 = it.tr * BM, col0 = it.tc * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
+    const int ncol = 2 * a.nfld;
+    const T *A0 = (const T *)a.tab + b.off_kr;
+    const T *A1 = A0 + (int64_t)b.Kp * b.Rp;
+    const T *spec = (const T *)a.in;
+    const int64_t sb = spec_base(a.trunc, m);
+
+    V acc[2][FM][FN];
+    for (int p = 0; p < 2; ++p)
+        for (int i = 0; i < FM; ++i)
+            for (int j = 0; j < FN; ++j) acc[p][i][j] = V{};
+
+    for (int kk = 0; kk < b.K0; kk += BK) {
+        // table tile: rows kappa = k, columns i = ring (contiguous in [p][k][r])
+        for (int e = tid; e < 2 * BK * BM; e += 256) {
+            int p = e / (BK * BM), rem = e - p * BK * BM, q = rem / BM, i = rem - q * BM;
+            const T *Ap = p ? A1 : A0;
+            As[p][q][i] = Ap[(int64_t)(kk + q) * b.Rp + row0 + i];
+        }
+        // spectral tile: for each field, 2 BK consecutive n (both parities)
+        for (int e = tid; e < (BN / 2) * (2 * BK); e += 256) {
+            int fl = e / (2 * BK), t = e - fl * (2 * BK);
+            int f = col0 / 2 + fl, nrel = 2 * kk + t;
+            T re = 0, im = 0;
+            if (f < a.nfld && m + nrel <= a.trunc) {
+                int64_t o = 2 * ((int64_t)f * a.nspec + sb + nrel);
+                re = spec[o];
+                im = (m == 0) ? T(0) : spec[o + 1];
+            }
+            int p = t & 1, q = t >> 1;
+            Bs[p][q][2 * fl] = re;
+            Bs[p][q][2 * fl + 1] = im;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < BK; q += 4) {
+            const int qq = q + (lane >> 4);
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                T av[FM], bv[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) av[i] = As[p][qq][wr + i * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < FN; ++j) bv[j] = Bs[p][qq][wc + j * 16 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) acc[p][i][j] = mfma16x16x4(av[i], bv[j], acc[p][i][j]);
+            }
+        }
+        __syncthreads();
+    }
+
+    T *four = (T *)a.out;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int r = row0 + wr + i * 16 + 4 * (lane >> 4) + v;
+                int c = col0 + wc + j * 16 + (lane & 15);
+                if (r < b.R && c < ncol) {
+                    T s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
+                    int jn = b.j0 + r, js = a.nlat - 1 - jn;
+                    four[2 * (a.rings[jn].four_off + (int64_t)m * a.nfld) + c] = s0 + s1;
+                    four[2 * (a.rings[js].four_off + (int64_t)m * a.nfld) + c] = s0 - s1;
+                }
+            }
+}
+
+template <typename T, int BM, int BN, int BK>
+__global__ __launch_bounds__(256) void k_leg_dir_mfma(GemmArgs a)
+{
+    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+    constexpr int LDA = BM + 4, LDB = BN + 4;
+    typedef typename Acc<T>::type V;
+    __shared__ T As[2][BK][LDA];
+    __shared__ T Bs[2][BK][LDB];
+
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const GemmItem it = a.items[item];
+    if (it.m < 0) return;
+    const int m = it.m;
+    const MBlock b = a.mb[m];
+    const int row0 = it.tr * BM, col0 = it.tc * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
+    const int ncol = 2 * a.nfld;
+    const T *A0 = (const T *)a.tab + b.off_rk;
+    const T *A1 = A0 + (int64_t)b.Rp * b.Kp;
+    const T *four = (const T *)a.in;
+
+    V acc[2][FM][FN];
+    for (int p = 0; p < 2; ++p)
+        for (int i = 0; i < FM; ++i)
+            for (int j = 0; j < FN; ++j) acc[p][i][j] = V{};
+
+    for (int rr = 0; rr < b.R; rr += BK) {
+        // table tile: rows kappa = ring, columns i = k (contiguous in [p][r][k])
+        for (int e = tid; e < 2 * BK * BM; e += 256) {
+            int p = e / (BK * BM), rem = e - p * BK * BM, q = rem / BM, i = rem - q * BM;
+            const T *Ap = p ? A1 : A0;
+            As[p][q][i] = Ap[(int64_t)(rr + q) * b.Kp + row0 + i];
+        }
+        // Fourier tile folded over the hemispheres
+        for (int e = tid; e < BK * BN; e += 256) {
+            int q = e / BN, cl = e - q * BN;
+            int r = rr + q, c = col0 + cl;
+            T b0 = 0, b1 = 0;
+            if (r < b.R && c < ncol) {
+                int jn = b.j0 + r, js = a.nlat - 1 - jn;
+                T gn = four[2 * (a.rings[jn].four_off + (int64_t)m * a.nfld) + c];
+                T gs = four[2 * (a.rings[js].four_off + (int64_t)m * a.nfld) + c];
+                T q_r = a.adjoint ? T(1) : T(0.5 * a.rings[jn].w);
+                b0 = q_r * (gn + gs);
+                b1 = q_r * (gn - gs);
+            }
+            Bs[0][q][cl] = b0;
+            Bs[1][q][cl] = b1;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < BK; q += 4) {
+            const int qq = q + (lane >> 4);
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                T av[FM], bv[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) av[i] = As[p][qq][wr + i * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < FN; ++j) bv[j] = Bs[p][qq][wc + j * 16 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) acc[p][i][j] = mfma16x16x4(av[i], bv[j], acc[p][i][j]);
+            }
+        }
+        __syncthreads();
+    }
+
+    T *spec = (T *)a.out;
+    const int64_t sb = spec_base(a.trunc, m);
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int k = row0 + wr + i * 16 + 4 * (lane >> 4) + v;
+                    int c = col0 + wc + j * 16 + (lane & 15);
+                    int nrel = p + 2 * k;
+                    if (m + nrel <= a.trunc && c < ncol) {
+                        T val = acc[p][i][j][v];
+                        if (m == 0 && (c & 1)) val = 0;
+                        spec[2 * ((int64_t)(c >> 1) * a.nspec + sb + nrel) + (c & 1)] = val;
+                    }
+                }
+}
+
+// ---------------------------------------------------------------------------
+// Split BF16 (hi + lo) with FP32 accumulation: 3 MFMAs per tile product
+// (hi*hi + hi*lo + lo*hi).  16x16x32 MFMA: lane l supplies A[l%16][8(l/16)..+7]
+// and B[8(l/16)..+7][l%16]; LDS tiles are row-major with kappa contiguous:
+// As[p][h][i][kappa], Bs[p][h][j][kappa] (h = hi, lo).
+// ---------------------------------------------------------------------------
+__device__ inline unsigned short bf16_rne(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+__device__ inline void split_bf16(float x, unsigned short &hi, unsigned short &lo)
+{
+    hi = bf16_rne(x);
+    lo = bf16_rne(x - bf16_to_f(hi));
+}
+
+__device__ inline f32x4 mfma_bf16(const unsigned short *pa, const unsigned short *pb, f32x4 c)
+{
+    bf16x8 av = *reinterpret_cast<const bf16x8 *>(pa);
+    bf16x8 bv = *reinterpret_cast<const bf16x8 *>(pb);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+}
+
+template <int BM, int BN, int BK, bool INVERSE>
+__global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
+{
+    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+    constexpr int LDK = BK + 8;  // 16-byte aligned rows, staggered banks
+    __shared__ __attribute__((aligned(16))) unsigned short As[2][2][BM][LDK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][2][BN][LDK];
+
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const GemmItem it = a.items[item];
+    if (it.m < 0) return;
+    const int m = it.m;
+    const MBlock b = a.mb[m];
+    const int row0 = it.tr * BM, col0 = it.tc * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
+    const int ncol = 2 * a.nfld;
+    const int64_t sb = spec_base(a.trunc, m);
+    // A operand rows are contiguous in kappa: inverse reads [p][r][k], direct [p][k][r]
+    const int64_t off = INVERSE ? b.off_rk : b.off_kr;
+    const int lda = INVERSE ? b.Kp : b.Rp;
+    const int64_t pstride = (int64_t)b.Rp * b.Kp;
+    const unsigned short *Th = (const unsigned short *)a.tab + off;
+    const unsigned short *Tl = (const unsigned short *)a.tab_lo + off;
+    const int kend = INVERSE ? b.K0 : b.R;
+
+    f32x4 acc[2][FM][FN];
+    for (int p = 0; p < 2; ++p)
+        for (int i = 0; i < FM; ++i)
+            for (int j = 0; j < FN; ++j) acc[p][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int kk = 0; kk < kend; kk += BK) {
+        // table tile: 2 parities x 2 halves x BM rows x BK kappa, 8 per 16-byte load
+        constexpr int CH = BK / 8;
+        for (int e = tid; e < 2 * 2 * BM * CH; e += 256) {
+            int p = e / (2 * BM * CH), rem = e - p * 2 * BM * CH;
+            int hl = rem / (BM * CH);
+            rem -= hl * BM * CH;
+            int i = rem / CH, ch = rem - i * CH;
+            const unsigned short *src = (hl ? Tl : Th) + p * pstride + (int64_t)(row0 + i) * lda + kk + ch * 8;
+            *reinterpret_cast<uint4 *>(&As[p][hl][i][ch * 8]) = *reinterpret_cast<const uint4 *>(src);
+        }
+        if (INVERSE) {
+            const float *spec = (const float *)a.in;
+            for (int e = tid; e < (BN / 2) * (2 * BK); e += 256) {
+                int fl = e / (2 * BK), t = e - fl * (2 * BK);
+                int f = col0 / 2 + fl, nrel = 2 * kk + t;
+                float re = 0.f, im = 0.f;
+                if (f < a.nfld && m + nrel <= a.trunc) {
+                    int64_t o = 2 * ((int64_t)f * a.nspec + sb + nrel);
+                    re = spec[o];
+                    im = (m == 0) ? 0.f : spec[o + 1];
+                }
+                int p = t & 1, q = t >> 1;
+                unsigned short h, l;
+                split_bf16(re, h, l);
+                Bs[p][0][2 * fl][q] = h;
+                Bs[p][1][2 * fl][q] = l;
+                split_bf16(im, h, l);
+                Bs[p][0][2 * fl + 1][q] = h;
+                Bs[p][1][2 * fl + 1][q] = l;
+            }
+        } else {
+            const float *four = (const float *)a.in;
+            for (int e = tid; e < BK * BN; e += 256) {
+                int q = e / BN, cl = e - q * BN;
+                int r = kk + q, c = col0 + cl;
+                float b0 = 0.f, b1 = 0.f;
+                if (r < b.R && c < ncol) {
+                    int jn = b.j0 + r, js = a.nlat - 1 - jn;
+                    float gn = four[2 * (a.rings[jn].four_off + (int64_t)m * a.nfld) + c];
+                    float gs = four[2 * (a.rings[js].four_off + (int64_t)m * a.nfld) + c];
+                    float q_r = a.adjoint ? 1.f : (float)(0.5 * a.rings[jn].w);
+                    b0 = q_r * (gn + gs);
+                    b1 = q_r * (gn - gs);
+                }
+                unsigned short h, l;
+                split_bf16(b0, h, l);
+                Bs[0][0][cl][q] = h;
+                Bs[0][1][cl][q] = l;
+                split_bf16(b1, h, l);
+                Bs[1][0][cl][q] = h;
+                Bs[1][1][cl][q] = l;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < BK; q += 32) {
+            const int kq = q + 8 * (lane >> 4);
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        const int ai = wr + i * 16 + (lane & 15), bj = wc + j * 16 + (lane & 15);
+                        f32x4 c = acc[p][i][j];
+                        c = mfma_bf16(&As[p][0][ai][kq], &Bs[p][1][bj][kq], c);
+                        c = mfma_bf16(&As[p][1][ai][kq], &Bs[p][0][bj][kq], c);
+                        c = mfma_bf16(&As[p][0][ai][kq], &Bs[p][0][bj][kq], c);
+                        acc[p][i][j] = c;
+                    }
+        }
+        __syncthreads();
+    }
+
+    const float unscale = ldexpf(1.f, -b.e);
+    if (INVERSE) {
+        float *four = (float *)a.out;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    int r = row0 + wr + i * 16 + 4 * (lane >> 4) + v;
+                    int c = col0 + wc + j * 16 + (lane & 15);
+                    if (r < b.R && c < ncol) {
+                        float s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
+                        int jn = b.j0 + r, js = a.nlat - 1 - jn;
+                        four[2 * (a.rings[jn].four_off + (int64_t)m * a.nfld) + c] = (s0 + s1) * unscale;
+                        four[2 * (a.rings[js].four_off + (int64_t)m * a.nfld) + c] = (s0 - s1) * unscale;
+                    }
+                }
+    } else {
+        float *spec = (float *)a.out;
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int k = row0 + wr + i * 16 + 4 * (lane >> 4) + v;
+                        int c = col0 + wc + j * 16 + (lane & 15);
+                        int nrel = p + 2 * k;
+                        if (m + nrel <= a.trunc && c < ncol) {
+                            float val = acc[p][i][j][v] * unscale;
+                            if (m == 0 && (c & 1)) val = 0.f;
+                            spec[2 * ((int64_t)(c >> 1) * a.nspec + sb + nrel) + (c & 1)] = val;
+                        }
+                    }
+    }
+}
+
+GemmArgs make_args(const Plan &p, bool inverse_shape, const void *in, void *out, bool adjoint)
+{
+    GemmArgs a{};
+    a.mb = p.d_mb;
+    a.items = inverse_shape ? p.d_inv_items : p.d_dir_items;
+    a.rings = p.d_rings;
+    a.in = in;
+    a.out = out;
+    a.trunc = p.trunc;
+    a.nlat = p.nlat;
+    a.nfld = p.nfld;
+    a.adjoint = adjoint ? 1 : 0;
+    a.nspec = p.nspec;
+    if (p.prec == SHTX_BF16X3) {
+        a.tab = inverse_shape ? p.d_tab_rk : p.d_tab_kr;
+        a.tab_lo = inverse_shape ? p.d_tab_rk_lo : p.d_tab_kr_lo;
+    } else {
+        a.tab = inverse_shape ? p.d_tab_kr : p.d_tab_rk;
+        a.tab_lo = nullptr;
+    }
+    return a;
+}
+
+// Host check that every tile of a work list reads and writes inside the
+// table, Fourier and spectral arrays for the given tile sizes.
+bool check_items(const Plan &p, const std::vector<GemmItem> &items, bool inverse_shape, int bm, int bn,
+                 int bk)
+{
+    if (items.empty() || items.size() % kXcds) return false;
+    int ncol = 2 * p.nfld;
+    for (const GemmItem &it : items) {
+        if (it.m < 0) continue;
+        if (it.m > p.trunc) return false;
+        const MBlock &b = p.mb[it.m];
+        if (it.tc < 0 || it.tc * bn >= ncol) return false;
+        if (inverse_shape) {
+            if (it.tr < 0 || it.tr * bm >= b.R || (it.tr + 1) * bm > b.Rp) return false;
+            if ((int64_t)((b.K0 + bk - 1) / bk) * bk > b.Kp) return false;
+        } else {
+            if (it.tr < 0 || it.tr * bm >= b.K0 || (it.tr + 1) * bm > b.Kp) return false;
+            if ((int64_t)((b.R + bk - 1) / bk) * bk > b.Rp) return false;
+        }
+        if (b.j0 + b.R > p.nlat / 2) return false;
+    }
+    return true;
+}
+
+}  // namespace
+
+hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, hipStream_t s)
+{
+    GemmArgs a = make_args(p, true, spec, four, false);
+    int grid = (int)p.inv_items.size();
+    if (grid == 0) return hipSuccess;
+    if (p.prec == SHTX_FP64) {
+        if (!check_items(p, p.inv_items, true, 64, 64, 16)) return hipErrorInvalidValue;
+        k_leg_inv_mfma<double, 64, 64, 16><<<grid, 256, 0, s>>>(a);
+    } else if (p.prec == SHTX_FP32) {
+        if (!check_items(p, p.inv_items, true, 128, 128, 16)) return hipErrorInvalidValue;
+        k_leg_inv_mfma<float, 128, 128, 16><<<grid, 256, 0, s>>>(a);
+    } else {
+        if (!check_items(p, p.inv_items, true, 128, 128, 32)) return hipErrorInvalidValue;
+        k_leg_bf16x3<128, 128, 32, true><<<grid, 256, 0, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm_direct(const Plan &p, const void *four, void *spec, bool adjoint, hipStream_t s)
+{
+    GemmArgs a = make_args(p, false, four, spec, adjoint);
+    int grid = (int)p.dir_items.size();
+    if (p.prec == SHTX_FP64) {
+        if (!check_items(p, p.dir_items, false, 64, 64, 16)) return hipErrorInvalidValue;
+        k_leg_dir_mfma<double, 64, 64, 16><<<grid, 256, 0, s>>>(a);
+    } else if (p.prec == SHTX_FP32) {
+        if (!check_items(p, p.dir_items, false, 128, 128, 16)) return hipErrorInvalidValue;
+        k_leg_dir_mfma<float, 128, 128, 16><<<grid, 256, 0, s>>>(a);
+    } else {
+        if (!check_items(p, p.dir_items, false, 128, 128, 32)) return hipErrorInvalidValue;
+        k_leg_bf16x3<128, 128, 32, false><<<grid, 256, 0, s>>>(a);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace shtx

@@ -1,0 +1,287 @@
+// Plan-time kernels: Gauss-Legendre nodes/weights and the P̄_n^m tables.
+//
+// Everything here runs in FP64 on the device.  The nodes are Newton roots of
+// P_nlat polished in double-double so that each stored node is the double
+// nearest to the true root; the tables follow the standard three-term
+// recurrence in n for each fixed m from the sectoral seed P̄_m^m.  The paper
+// (Section 3.1.1) keeps all such data resident on the GPU.
+#include <cmath>
+
+#include "shtx_internal.h"
+
+namespace shtx {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// double-double arithmetic (hi + lo, |lo| <= ulp(hi) / 2)
+// ---------------------------------------------------------------------------
+struct dd {
+    double hi, lo;
+};
+
+__device__ inline dd quick_two_sum(double a, double b)
+{
+    double s = a + b;
+    return {s, b - (s - a)};
+}
+
+__device__ inline dd two_sum(double a, double b)
+{
+    double s = a + b;
+    double bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
+}
+
+__device__ inline dd two_prod(double a, double b)
+{
+    double p = a * b;
+    return {p, fma(a, b, -p)};
+}
+
+__device__ inline dd dd_add(dd a, dd b)
+{
+    dd s = two_sum(a.hi, b.hi);
+    dd t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = quick_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return quick_two_sum(s.hi, s.lo);
+}
+
+__device__ inline dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+
+__device__ inline dd dd_mul(dd a, dd b)
+{
+    dd p = two_prod(a.hi, b.hi);
+    p.lo += a.hi * b.lo + a.lo * b.hi;
+    return quick_two_sum(p.hi, p.lo);
+}
+
+__device__ inline dd dd_mul_d(dd a, double b)
+{
+    dd p = two_prod(a.hi, b);
+    p.lo += a.lo * b;
+    return quick_two_sum(p.hi, p.lo);
+}
+
+__device__ inline dd dd_div(dd a, dd b)
+{
+    double q1 = a.hi / b.hi;
+    dd r = dd_add(a, dd_neg(dd_mul_d(b, q1)));
+    double q2 = r.hi / b.hi;
+    r = dd_add(r, dd_neg(dd_mul_d(b, q2)));
+    double q3 = r.hi / b.hi;
+    dd q = quick_two_sum(q1, q2);
+    return dd_add(q, dd{q3, 0.0});
+}
+
+// P_n(x) and P_{n-1}(x) (unnormalised Legendre polynomials) in double-double
+// at a double-double abscissa, by l P_l = (2l-1) x P_{l-1} - (l-1) P_{l-2}.
+__device__ void legendre_dd(int n, dd x, dd *pn, dd *pn1)
+{
+    dd p0 = {1.0, 0.0}, p1 = x;
+    for (int l = 2; l <= n; ++l) {
+        dd t = dd_mul_d(dd_mul(p1, x), (double)(2 * l - 1));
+        t = dd_add(t, dd_neg(dd_mul_d(p0, (double)(l - 1))));
+        dd p2 = dd_div(t, dd{(double)l, 0.0});
+        p0 = p1;
+        p1 = p2;
+    }
+    *pn = p1;
+    *pn1 = p0;
+}
+
+// P'_n(x) = n (x P_n - P_{n-1}) / (x^2 - 1) in double-double.
+__device__ dd dlegendre_dd(int n, dd x, dd pn, dd pn1)
+{
+    dd num = dd_mul_d(dd_add(dd_mul(x, pn), dd_neg(pn1)), (double)n);
+    dd den = dd_add(dd_mul(x, x), dd{-1.0, 0.0});
+    return dd_div(num, den);
+}
+
+// One thread per northern node j < nlat / 2.
+__global__ void k_gauss_nodes(int nlat, double *mu, double *w)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nlat / 2) return;
+    double x = cos(M_PI * (j + 0.75) / (nlat + 0.5));
+    for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = x;
+        for (int l = 2; l <= nlat; ++l) {
+            double p2 = ((2.0 * l - 1.0) * x * p1 - (l - 1.0) * p0) / l;
+            p0 = p1;
+            p1 = p2;
+        }
+        double dp = nlat * (x * p1 - p0) / (x * x - 1.0);
+        double dx = p1 / dp;
+        x -= dx;
+        if (fabs(dx) < 1e-16) break;
+    }
+    // Two Newton steps in double-double; the normalised hi word is then the
+    // double nearest to the root.
+    dd r = {x, 0.0};
+    for (int it = 0; it < 2; ++it) {
+        dd pn, pn1;
+        legendre_dd(nlat, r, &pn, &pn1);
+        dd dp = dlegendre_dd(nlat, r, pn, pn1);
+        r = dd_add(r, dd_neg(dd_div(pn, dp)));
+    }
+    dd pn, pn1;
+    legendre_dd(nlat, r, &pn, &pn1);
+    dd dp = dlegendre_dd(nlat, r, pn, pn1);
+    // w = 2 / ((1 - x)(1 + x) P'(x)^2) at the double-double root
+    dd omx = dd_add(dd{1.0, 0.0}, dd_neg(r));
+    dd opx = dd_add(dd{1.0, 0.0}, r);
+    dd den = dd_mul(dd_mul(omx, opx), dd_mul(dp, dp));
+    dd wq = dd_div(dd{2.0, 0.0}, den);
+    mu[j] = r.hi;
+    w[j] = wq.hi;
+    mu[nlat - 1 - j] = -r.hi;
+    w[nlat - 1 - j] = wq.hi;
+}
+
+// Sectoral seeds P̄_m^m(mu_j) = prod_{k<=m} sqrt((2k+1)/(2k)) s_j, one thread per
+// northern ring, s_j = sqrt((1 - mu_j)(1 + mu_j)).
+__global__ void k_sectoral(int nl, int trunc, const double *mu, double *diag)
+{
+    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nl) return;
+    double x = mu[j];
+    double s = sqrt((1.0 - x) * (1.0 + x));
+    double pmm = 1.0;
+    double *d = diag + (int64_t)j * (trunc + 1);
+    d[0] = 1.0;
+    for (int k = 1; k <= trunc; ++k) {
+        pmm *= sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
+        d[k] = pmm;
+    }
+}
+
+__device__ inline unsigned short bf16_rne(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// Column recurrence over n for one (m, ring).  MODE 0: per-m max |P̄| only;
+// MODE 1: store FP64; MODE 2: store FP32; MODE 3: store split BF16 hi + lo
+// scaled by 2^e_m.  Both table layouts are written: kr = [p][k][r] and
+// rk = [p][r][k] (k = (n - m - p) / 2).
+template <int MODE>
+__global__ void k_legendre_table(int trunc, const double *mu, const double *diag, MBlock *mbs,
+                                 unsigned long long *mmax, void *tab_kr, void *tab_rk,
+                                 void *lo_kr, void *lo_rk)
+{
+    const int m = blockIdx.y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const MBlock b = mbs[m];
+    if (MODE == 3 && r == 0 && blockIdx.x == 0) {
+        // exponent: max * 2^e in [1/2, 1)
+        double mx = __longlong_as_double((long long)mmax[m]);
+        int E = 0;
+        if (mx > 0.0) frexp(mx, &E);
+        mbs[m].e = -E;
+    }
+    if (r >= b.R) return;
+    const int j = b.j0 + r;
+    const double x = mu[j];
+    double scale = 1.0;
+    if (MODE == 3) {
+        double mx = __longlong_as_double((long long)mmax[m]);
+        int E = 0;
+        if (mx > 0.0) frexp(mx, &E);
+        scale = ldexp(1.0, -E);
+    }
+    double vmax = 0.0;
+    auto put = [&](int n, double v) {
+        if (MODE == 0) {
+            vmax = fmax(vmax, fabs(v));
+            return;
+        }
+        int t = n - m, par = t & 1, k = t >> 1;
+        int64_t ikr = b.off_kr + (int64_t)par * b.Kp * b.Rp + (int64_t)k * b.Rp + r;
+        int64_t irk = b.off_rk + (int64_t)par * b.Rp * b.Kp + (int64_t)r * b.Kp + k;
+        if (MODE == 1) {
+            ((double *)tab_kr)[ikr] = v;
+            ((double *)tab_rk)[irk] = v;
+        } else if (MODE == 2) {
+            ((float *)tab_kr)[ikr] = (float)v;
+            ((float *)tab_rk)[irk] = (float)v;
+        } else {
+            double vs = v * scale;
+            unsigned short hi = bf16_rne((float)vs);
+            unsigned short lo = bf16_rne((float)(vs - (double)bf16_to_f(hi)));
+            ((unsigned short *)tab_kr)[ikr] = hi;
+            ((unsigned short *)tab_rk)[irk] = hi;
+            ((unsigned short *)lo_kr)[ikr] = lo;
+            ((unsigned short *)lo_rk)[irk] = lo;
+        }
+    };
+    double p0 = diag[(int64_t)j * (trunc + 1) + m];
+    put(m, p0);
+    if (m < trunc) {
+        double p1 = sqrt(2.0 * m + 3.0) * x * p0;
+        put(m + 1, p1);
+        for (int n = m + 2; n <= trunc; ++n) {
+            double nn = (double)n * n, mm = (double)m * m;
+            double a = sqrt((4.0 * nn - 1.0) / (nn - mm));
+            double bb = sqrt((2.0 * n + 1.0) * (n - 1.0 - m) * (n - 1.0 + m) / ((2.0 * n - 3.0) * (nn - mm)));
+            double p2 = a * x * p1 - bb * p0;
+            put(n, p2);
+            p0 = p1;
+            p1 = p2;
+        }
+    }
+    if (MODE == 0 && vmax > 0.0) atomicMax(mmax + m, (unsigned long long)__double_as_longlong(vmax));
+}
+
+}  // namespace
+
+hipError_t launch_gauss_nodes(int nlat, double *mu, double *w, hipStream_t s)
+{
+    if (nlat < 2 || nlat % 2) return hipErrorInvalidValue;
+    int half = nlat / 2;
+    k_gauss_nodes<<<(half + 127) / 128, 128, 0, s>>>(nlat, mu, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_legendre_tables(Plan &p, hipStream_t s)
+{
+    const int NL = p.nlat / 2, N = p.trunc;
+    if (p.mb.size() != (size_t)N + 1) return hipErrorInvalidValue;
+    // host check: every table write of every (m, r) lands inside the allocation
+    for (const MBlock &b : p.mb) {
+        if (b.R > b.Rp || b.K0 > b.Kp || b.j0 + b.R > NL) return hipErrorInvalidValue;
+        if (b.off_kr + 2 * (int64_t)b.Kp * b.Rp > p.tab_elems) return hipErrorInvalidValue;
+    }
+    size_t el = p.prec == SHTX_FP64 ? 8 : p.prec == SHTX_FP32 ? 4 : 2;
+    hipError_t e = hipMemsetAsync(p.d_tab_kr, 0, el * p.tab_elems, s);
+    if (e == hipSuccess) e = hipMemsetAsync(p.d_tab_rk, 0, el * p.tab_elems, s);
+    if (e == hipSuccess && p.d_tab_kr_lo) e = hipMemsetAsync(p.d_tab_kr_lo, 0, el * p.tab_elems, s);
+    if (e == hipSuccess && p.d_tab_rk_lo) e = hipMemsetAsync(p.d_tab_rk_lo, 0, el * p.tab_elems, s);
+    if (e == hipSuccess) e = hipMemsetAsync(p.d_mmax, 0, sizeof(unsigned long long) * (N + 1), s);
+    if (e != hipSuccess) return e;
+    k_sectoral<<<(NL + 127) / 128, 128, 0, s>>>(NL, N, p.d_mu, p.d_diag);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    dim3 grid((NL + 127) / 128, N + 1);
+    if (p.prec == SHTX_FP64) {
+        k_legendre_table<1><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, p.d_tab_kr,
+                                                  p.d_tab_rk, nullptr, nullptr);
+    } else if (p.prec == SHTX_FP32) {
+        k_legendre_table<2><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, p.d_tab_kr,
+                                                  p.d_tab_rk, nullptr, nullptr);
+    } else {
+        k_legendre_table<0><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, nullptr,
+                                                  nullptr, nullptr, nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        k_legendre_table<3><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, p.d_tab_kr,
+                                                  p.d_tab_rk, p.d_tab_kr_lo, p.d_tab_rk_lo);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace shtx

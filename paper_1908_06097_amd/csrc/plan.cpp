@@ -1,0 +1,417 @@
+// Plan construction for libshtx: ring geometry, Legendre table layout, GEMM
+// and ring-FFT work lists, FFT twiddle tables, device allocations, and the
+// device-side generation of Gauss nodes and P̄_n^m tables.
+//
+// The paper (Section 3.1.1) keeps the transform's data resident on the GPU
+// across time steps; here everything a transform needs (tables, twiddles,
+// work lists, the Fourier workspace) is allocated once per plan so that the
+// transform calls themselves never allocate.
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+
+#include "shtx_internal.h"
+
+namespace shtx {
+
+namespace {
+
+int ring_cutoff(int trunc, int nlon)
+{
+    int m = (nlon - 1) / 2;
+    return m < trunc ? m : trunc;
+}
+
+int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
+
+// Factor n over {2, 3, 5, 7}; returns the unfactored remainder.
+int smooth_factor(int n, std::vector<int> &f)
+{
+    f.clear();
+    for (int p : {2, 3, 5, 7})
+        while (n % p == 0) {
+            f.push_back(p);
+            n /= p;
+        }
+    return n;
+}
+
+// Stockham radices for a 7-smooth length: as many radix-8 passes as the
+// power of two allows, then a 4 or 2, then the odd primes.
+std::vector<int> radices_for(int L)
+{
+    std::vector<int> f;
+    smooth_factor(L, f);
+    int twos = 0;
+    std::vector<int> odd;
+    for (int p : f) {
+        if (p == 2)
+            ++twos;
+        else
+            odd.push_back(p);
+    }
+    std::vector<int> r;
+    for (; twos >= 3; twos -= 3) r.push_back(8);
+    if (twos == 2) r.push_back(4);
+    if (twos == 1) r.push_back(2);
+    r.insert(r.end(), odd.begin(), odd.end());
+    return r;
+}
+
+template <class T>
+hipError_t upload(T **dst, const std::vector<T> &src)
+{
+    if (src.empty()) {
+        *dst = nullptr;
+        return hipSuccess;
+    }
+    hipError_t e = hipMalloc(dst, sizeof(T) * src.size());
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+void gemm_tiles(int prec, int *inv_bm, int *inv_bn, int *dir_bm, int *dir_bn)
+{
+    if (prec == SHTX_FP64) {
+        *inv_bm = 64; *inv_bn = 64; *dir_bm = 64; *dir_bn = 64;
+    } else {
+        *inv_bm = 128; *inv_bn = 128; *dir_bm = 128; *dir_bn = 128;
+    }
+}
+
+// Long-double mixed-radix DFT (forward) over a 7-smooth length, used once per
+// ring length at plan time for the Bluestein filter spectrum.
+static void dft_ld(std::complex<long double> *x, int n, int stride,
+                   const std::vector<std::complex<long double>> &tw, int N,
+                   std::vector<std::complex<long double>> &tmp)
+{
+    if (n == 1) return;
+    int p = 2;
+    for (int q : {2, 3, 5, 7})
+        if (n % q == 0) {
+            p = q;
+            break;
+        }
+    int m = n / p;
+    // decimation in time: sub-sequence r holds x[k p + r]
+    std::vector<std::complex<long double>> sub((size_t)n);
+    for (int r = 0; r < p; ++r)
+        for (int k = 0; k < m; ++k) sub[(size_t)r * m + k] = x[(size_t)(k * p + r) * stride];
+    for (int r = 0; r < p; ++r) dft_ld(sub.data() + (size_t)r * m, m, 1, tw, N, tmp);
+    int step = N / n;  // tw[t * step] = exp(-2 pi i t / n)
+    for (int k = 0; k < m; ++k)
+        for (int q = 0; q < p; ++q) {
+            std::complex<long double> acc = 0;
+            int kk = k + q * m;
+            for (int r = 0; r < p; ++r) {
+                int t = (int)(((int64_t)r * kk) % n);
+                acc += sub[(size_t)r * m + k] * tw[(size_t)t * step];
+            }
+            x[(size_t)kk * stride] = acc;
+        }
+}
+
+void bluestein_filter(int h, int L, std::vector<long double> &re, std::vector<long double> &im)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<std::complex<long double>> b((size_t)L, 0), tw((size_t)L), tmp;
+    for (int k = 0; k < L; ++k) tw[k] = std::polar(1.0L, -2.0L * pi * k / L);
+    for (int j = 0; j < h; ++j) {
+        int64_t t = ((int64_t)j * j) % (2 * (int64_t)h);
+        std::complex<long double> c = std::polar(1.0L, -pi * (long double)t / h);  // chirp
+        b[j] = std::conj(c);
+        if (j > 0) b[L - j] = std::conj(c);
+    }
+    dft_ld(b.data(), L, 1, tw, L, tmp);
+    re.resize(L);
+    im.resize(L);
+    for (int k = 0; k < L; ++k) {
+        re[k] = b[k].real() / L;
+        im[k] = b[k].imag() / L;
+    }
+}
+
+void free_plan(Plan &p)
+{
+    void *ptrs[] = {p.d_mu, p.d_w, p.d_diag, p.d_tab_kr, p.d_tab_rk, p.d_tab_kr_lo,
+                    p.d_tab_rk_lo, p.d_mmax, p.d_mb, p.d_inv_items, p.d_dir_items,
+                    p.d_rings, p.d_fft_items, p.d_twid, p.d_four};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    for (auto &g : p.graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    for (auto e : p.ev_start) (void)hipEventDestroy(e);
+    for (auto e : p.ev_stop) (void)hipEventDestroy(e);
+    p = Plan();
+}
+
+#define PLAN_TRY(expr)                                   \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
+        if (e_ != hipSuccess) {                          \
+            (void)hipGetLastError();                     \
+            return e_ == hipErrorOutOfMemory ? SHTX_ENOMEM : SHTX_EHIP; \
+        }                                                \
+    } while (0)
+
+int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, int prec,
+               unsigned flags, hipStream_t stream)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    if (trunc < 0 || nfld < 1 || nlat < 2) return SHTX_EINVAL;
+    if (grid != SHTX_GRID_FULL && grid != SHTX_GRID_OCTAHEDRAL) return SHTX_EINVAL;
+    if (prec != SHTX_FP64 && prec != SHTX_FP32 && prec != SHTX_BF16X3) return SHTX_EINVAL;
+    if (nlat % 2) return SHTX_EUNSUPPORTED;
+    if (grid == SHTX_GRID_FULL && (nlon_full < 2 || nlon_full % 2)) return nlon_full < 2 ? SHTX_EINVAL : SHTX_EUNSUPPORTED;
+    if (trunc > 4095 || nlat > 16384 || nfld > (1 << 20)) return SHTX_EUNSUPPORTED;
+
+    p.trunc = trunc;
+    p.grid = grid;
+    p.nlat = nlat;
+    p.nlon_full = nlon_full;
+    p.nfld = nfld;
+    p.prec = prec;
+    p.flags = flags;
+    const int N = trunc, NL = nlat / 2, F = nfld;
+
+    // ---- ring geometry ----------------------------------------------------
+    p.nlon.resize(nlat);
+    p.cutoff.resize(nlat);
+    for (int j = 0; j < nlat; ++j) {
+        int i = j < NL ? j : nlat - 1 - j;
+        p.nlon[j] = grid == SHTX_GRID_FULL ? nlon_full : 20 + 4 * i;
+        p.cutoff[j] = ring_cutoff(N, p.nlon[j]);
+        p.max_nlon = std::max(p.max_nlon, p.nlon[j]);
+    }
+    // The Legendre GEMM rows are the band of northern rings carrying m; it is
+    // contiguous because the cutoff never decreases towards the equator.
+    for (int j = 1; j < NL; ++j)
+        if (p.cutoff[j] < p.cutoff[j - 1]) return SHTX_EUNSUPPORTED;
+    p.nspec = (int64_t)(N + 1) * (N + 2) / 2;
+
+    // ---- m blocks -----------------------------------------------------------
+    p.mb.resize(N + 1);
+    int64_t off = 0;
+    double flops = 0.0;
+    for (int m = 0; m <= N; ++m) {
+        MBlock b{};
+        int j0 = NL;
+        for (int j = 0; j < NL; ++j)
+            if (p.cutoff[j] >= m) {
+                j0 = j;
+                break;
+            }
+        b.R = NL - j0;
+        b.j0 = j0;
+        b.K0 = (N - m) / 2 + 1;
+        b.K1 = (N - m + 1) / 2;
+        b.Rp = (int)round_up(std::max(b.R, 1), kTablePad);
+        b.Kp = (int)round_up(b.K0, kTablePad);
+        b.off_kr = off;
+        b.off_rk = off;
+        off += 2 * (int64_t)b.Kp * b.Rp;
+        p.mb[m] = b;
+        flops += 4.0 * F * (double)b.R * (N - m + 1);
+    }
+    p.tab_elems = off;
+    p.legendre_flops = flops;
+
+    // ---- Gauss nodes and Legendre tables (device, FP64) ---------------------
+    PLAN_TRY(hipMalloc(&p.d_mu, sizeof(double) * nlat));
+    PLAN_TRY(hipMalloc(&p.d_w, sizeof(double) * nlat));
+    PLAN_TRY(launch_gauss_nodes(nlat, p.d_mu, p.d_w, stream));
+
+    size_t tab_el = prec == SHTX_FP64 ? 8 : prec == SHTX_FP32 ? 4 : 2;
+    PLAN_TRY(hipMalloc(&p.d_tab_kr, tab_el * p.tab_elems));
+    PLAN_TRY(hipMalloc(&p.d_tab_rk, tab_el * p.tab_elems));
+    p.table_bytes = 2 * tab_el * p.tab_elems;
+    if (prec == SHTX_BF16X3) {
+        PLAN_TRY(hipMalloc(&p.d_tab_kr_lo, tab_el * p.tab_elems));
+        PLAN_TRY(hipMalloc(&p.d_tab_rk_lo, tab_el * p.tab_elems));
+        p.table_bytes *= 2;
+    }
+    PLAN_TRY(hipMalloc(&p.d_diag, sizeof(double) * (size_t)NL * (N + 1)));
+    PLAN_TRY(hipMalloc(&p.d_mmax, sizeof(unsigned long long) * (N + 1)));
+    PLAN_TRY(upload(&p.d_mb, p.mb));
+    PLAN_TRY(launch_legendre_tables(p, stream));
+    PLAN_TRY(hipStreamSynchronize(stream));
+    // exponents were decided on the device; refresh the host copy
+    PLAN_TRY(hipMemcpy(p.mb.data(), p.d_mb, sizeof(MBlock) * p.mb.size(), hipMemcpyDeviceToHost));
+    (void)hipFree(p.d_diag);
+    p.d_diag = nullptr;
+    (void)hipFree(p.d_mmax);
+    p.d_mmax = nullptr;
+
+    std::vector<double> w(nlat);
+    PLAN_TRY(hipMemcpy(w.data(), p.d_w, sizeof(double) * nlat, hipMemcpyDeviceToHost));
+
+    // ---- ring FFT plans and twiddle pool --------------------------------------
+    const bool dbl = prec == SHTX_FP64;
+    const int cap = dbl ? kFftCapF64 : kFftCapF32;
+    struct LenPlan {
+        int L, blue;
+        std::vector<int> rad;
+        int64_t tw, post, chirp, bhat;
+    };
+    std::map<int, LenPlan> lens;
+    std::vector<long double> pool;  // interleaved re, im
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int j = 0; j < nlat; ++j) {
+        int n = p.nlon[j];
+        if (lens.count(n)) continue;
+        int h = n / 2;
+        LenPlan lp{};
+        std::vector<int> f;
+        if (smooth_factor(h, f) == 1) {
+            lp.L = h;
+            lp.blue = 0;
+        } else {
+            int L = 2 * h - 1;
+            while (smooth_factor(L, f) != 1) ++L;
+            lp.L = L;
+            lp.blue = 1;
+        }
+        if (std::max(lp.L, h + 1) > cap) return SHTX_EUNSUPPORTED;
+        lp.rad = radices_for(lp.L);
+        if ((int)lp.rad.size() > kMaxRadices) return SHTX_EUNSUPPORTED;
+        auto push = [&](long double re, long double im) {
+            pool.push_back(re);
+            pool.push_back(im);
+        };
+        lp.tw = (int64_t)pool.size() / 2;
+        for (int k = 0; k < lp.L; ++k) {
+            long double a = 2.0L * pi * k / lp.L;
+            push(cosl(a), -sinl(a));
+        }
+        lp.post = (int64_t)pool.size() / 2;
+        for (int m = 0; m <= h; ++m) {
+            long double a = 2.0L * pi * m / n;
+            push(cosl(a), -sinl(a));
+        }
+        lp.chirp = lp.bhat = -1;
+        if (lp.blue) {
+            lp.chirp = (int64_t)pool.size() / 2;
+            for (int k = 0; k < h; ++k) {
+                int64_t t = ((int64_t)k * k) % (2 * (int64_t)h);
+                long double a = pi * (long double)t / h;
+                push(cosl(a), -sinl(a));
+            }
+            std::vector<long double> bre, bim;
+            bluestein_filter(h, lp.L, bre, bim);
+            lp.bhat = (int64_t)pool.size() / 2;
+            for (int k = 0; k < lp.L; ++k) push(bre[k], bim[k]);
+        }
+        lens[n] = lp;
+    }
+    size_t celem = dbl ? 16 : 8;
+    {
+        p.twid_elems = (int64_t)pool.size() / 2;
+        size_t bytes = pool.size() / 2 * celem;
+        PLAN_TRY(hipMalloc(&p.d_twid, bytes));
+        if (dbl) {
+            std::vector<double> host(pool.begin(), pool.end());
+            PLAN_TRY(hipMemcpy(p.d_twid, host.data(), bytes, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> host(pool.size());
+            for (size_t i = 0; i < pool.size(); ++i) host[i] = (float)pool[i];
+            PLAN_TRY(hipMemcpy(p.d_twid, host.data(), bytes, hipMemcpyHostToDevice));
+        }
+        p.workspace_bytes += bytes;
+    }
+
+    p.rings.resize(nlat);
+    int64_t goff = 0, foff = 0;
+    int lds_elems = 0;
+    std::vector<std::vector<FftItem>> fgroups;
+    std::vector<double> fcost;
+    for (int j = 0; j < nlat; ++j) {
+        RingDesc d{};
+        const LenPlan &lp = lens[p.nlon[j]];
+        d.n = p.nlon[j];
+        d.h = d.n / 2;
+        d.M = p.cutoff[j];
+        d.L = lp.L;
+        d.blue = lp.blue;
+        d.nrad = (int)lp.rad.size();
+        for (int r = 0; r < d.nrad; ++r) d.rad[r] = lp.rad[r];
+        d.lbuf = std::max(d.L, d.h + 1);
+        d.fb = std::max(1, std::min({F, cap / d.lbuf, 64}));
+        d.tw_off = lp.tw;
+        d.post_off = lp.post;
+        d.chirp_off = lp.chirp;
+        d.bhat_off = lp.bhat;
+        d.grid_off = goff;
+        d.four_off = foff;
+        d.w = w[j];
+        goff += d.n;
+        foff += (int64_t)(d.M + 1) * F;
+        p.rings[j] = d;
+        lds_elems = std::max(lds_elems, d.fb * d.lbuf);
+        std::vector<FftItem> g;
+        for (int f0 = 0; f0 < F; f0 += d.fb) g.push_back(FftItem{j, f0, std::min(d.fb, F - f0), 0});
+        fgroups.push_back(g);
+        fcost.push_back((double)F * d.L * (1 + d.blue) * std::log2((double)d.L + 1));
+    }
+    p.npts = goff;
+    p.nfour = foff / F;
+    p.fft_lds_bytes = lds_elems * (int)celem;
+    p.fft_items = layout_by_xcd(fgroups, fcost, FftItem{-1, 0, 0, 0});
+    PLAN_TRY(upload(&p.d_rings, p.rings));
+    PLAN_TRY(upload(&p.d_fft_items, p.fft_items));
+
+    // ---- GEMM work lists ----------------------------------------------------------
+    gemm_tiles(prec, &p.inv_bm, &p.inv_bn, &p.dir_bm, &p.dir_bn);
+    if (kTablePad % p.inv_bm || kTablePad % p.dir_bm) return SHTX_EUNSUPPORTED;
+    {
+        std::vector<std::vector<GemmItem>> gi, gd;
+        std::vector<double> ci, cd;
+        int ncol = 2 * F;
+        for (int m = 0; m <= N; ++m) {
+            const MBlock &b = p.mb[m];
+            double cost = (double)std::max(b.R, 1) * (N - m + 1) * ncol;
+            std::vector<GemmItem> a, c;
+            int ntc_i = (ncol + p.inv_bn - 1) / p.inv_bn;
+            int ntr_i = (b.R + p.inv_bm - 1) / p.inv_bm;
+            for (int tr = 0; tr < ntr_i; ++tr)
+                for (int tc = 0; tc < ntc_i; ++tc) a.push_back(GemmItem{m, tr, tc, 0});
+            int ntc_d = (ncol + p.dir_bn - 1) / p.dir_bn;
+            int ntk_d = (b.K0 + p.dir_bm - 1) / p.dir_bm;
+            for (int tk = 0; tk < ntk_d; ++tk)
+                for (int tc = 0; tc < ntc_d; ++tc) c.push_back(GemmItem{m, tk, tc, 0});
+            if (!a.empty()) {
+                gi.push_back(a);
+                ci.push_back(cost);
+            }
+            gd.push_back(c);
+            cd.push_back(cost);
+        }
+        p.inv_items = layout_by_xcd(gi, ci, GemmItem{-1, 0, 0, 0});
+        p.dir_items = layout_by_xcd(gd, cd, GemmItem{-1, 0, 0, 0});
+    }
+    PLAN_TRY(upload(&p.d_inv_items, p.inv_items));
+    PLAN_TRY(upload(&p.d_dir_items, p.dir_items));
+
+    // ---- Fourier workspace ---------------------------------------------------------
+    size_t four_bytes = (size_t)p.nfour * F * celem;
+    PLAN_TRY(hipMalloc(&p.d_four, four_bytes));
+    p.workspace_bytes += four_bytes;
+
+    if (flags & SHTX_FLAG_TIMING) {
+        p.ev_start.resize(Plan::kMaxTimed);
+        p.ev_stop.resize(Plan::kMaxTimed);
+        p.ev_kind.resize(Plan::kMaxTimed);
+        for (int i = 0; i < Plan::kMaxTimed; ++i) {
+            PLAN_TRY(hipEventCreate(&p.ev_start[i]));
+            PLAN_TRY(hipEventCreate(&p.ev_stop[i]));
+        }
+    }
+    PLAN_TRY(hipStreamSynchronize(stream));
+    p.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return SHTX_OK;
+}
+
+}  // namespace shtx

@@ -1,0 +1,179 @@
+// Internal declarations shared by the plan code and the HIP kernels of libshtx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/shtx.h"
+
+namespace shtx {
+
+// Legendre tables pad both the ring and the parity-k dimension of every m
+// block to a multiple of this, so that GEMM tiles (whose sizes divide it)
+// always read inside the block.
+constexpr int kTablePad = 128;
+
+// Ring-FFT kernels hold at most this many complex values of one block in LDS.
+constexpr int kFftCapF32 = 8192;  // 64 KiB
+constexpr int kFftCapF64 = 6144;  // 96 KiB
+constexpr int kFftThreads = 256;
+constexpr int kMaxRadices = 12;
+
+// One m block of the Legendre tables.
+struct MBlock {
+    int R;          // northern rings carrying m (M_j >= m): j0 .. j0 + R - 1
+    int j0;         // first such ring
+    int K0, K1;     // number of n = m + p + 2k <= N for parity p = 0, 1
+    int Rp, Kp;     // padded ring and parity-k extents
+    int e;          // power-of-two exponent applied to the stored split table
+    int pad_;
+    int64_t off_kr; // element offset of the [p][Kp][Rp] block (parity 1 at + Kp*Rp)
+    int64_t off_rk; // element offset of the [p][Rp][Kp] block (parity 1 at + Rp*Kp)
+};
+
+// One GEMM work item: wavenumber m, row tile, column tile (m < 0: no work).
+struct GemmItem {
+    int m, tr, tc, pad_;
+};
+
+// One ring of the grid (device copy of the FFT plan for that ring).
+struct RingDesc {
+    int n;        // ring length (even)
+    int h;        // n / 2: length of the complex FFT
+    int M;        // ring cutoff
+    int L;        // executed FFT length (h, or the Bluestein length >= 2h - 1)
+    int nrad;     // number of Stockham passes
+    int blue;     // 1 if the length-h DFT goes through Bluestein's convolution
+    int fb;       // fields per FFT block for this ring
+    int lbuf;     // complex LDS slots per field: max(L, h + 1)
+    int rad[kMaxRadices];
+    int64_t tw_off;     // W_L[k] = exp(-2 pi i k / L), k < L
+    int64_t post_off;   // exp(-2 pi i m / n), m <= h
+    int64_t chirp_off;  // Bluestein chirp exp(-pi i k^2 / h), k < h
+    int64_t bhat_off;   // Bluestein filter spectrum / L, L entries
+    int64_t grid_off;   // first point of the ring inside one grid field
+    int64_t four_off;   // first complex of the ring's [m][nfld] block
+    double w;           // Gauss weight
+};
+
+// One FFT work item: a ring and a run of fields (ring < 0: no work).
+struct FftItem {
+    int ring, f0, nf, pad_;
+};
+
+enum TransformKind { kInverse = 0, kDirect = 1, kInverseAdj = 2, kDirectAdj = 3 };
+
+struct Plan {
+    int trunc = 0, grid = 0, nlat = 0, nlon_full = 0, nfld = 0, prec = 0;
+    unsigned flags = 0;
+    int64_t nspec = 0, npts = 0, nfour = 0;
+    std::vector<int32_t> nlon;
+    std::vector<int> cutoff;
+    std::vector<MBlock> mb;
+    std::vector<RingDesc> rings;
+    int max_nlon = 0;
+
+    // GEMM tiling chosen at plan time (depends on precision).
+    int inv_bm = 0, inv_bn = 0, dir_bm = 0, dir_bn = 0;
+    std::vector<GemmItem> inv_items, dir_items;
+    std::vector<FftItem> fft_items;
+    int fft_lds_bytes = 0;
+
+    // Device memory.
+    double *d_mu = nullptr, *d_w = nullptr;  // nlat
+    double *d_diag = nullptr;                // [NL][N+1] sectoral seeds (plan time only)
+    void *d_tab_kr = nullptr, *d_tab_rk = nullptr;        // FP64/FP32 values or BF16 hi
+    void *d_tab_kr_lo = nullptr, *d_tab_rk_lo = nullptr;  // BF16 lo
+    unsigned long long *d_mmax = nullptr;                  // per-m max |P̄| bits (plan time)
+    MBlock *d_mb = nullptr;
+    GemmItem *d_inv_items = nullptr, *d_dir_items = nullptr;
+    RingDesc *d_rings = nullptr;
+    FftItem *d_fft_items = nullptr;
+    void *d_twid = nullptr;  // FFT twiddle pool (complex, grid precision)
+    int64_t twid_elems = 0;  // complex entries in the pool
+    void *d_four = nullptr;  // Fourier workspace [ring][m][nfld] complex
+    int64_t tab_elems = 0;   // elements per table layout
+    size_t table_bytes = 0, workspace_bytes = 0;
+    double legendre_flops = 0.0;
+    double plan_seconds = 0.0;
+
+    // Graph cache (one per transform kind, keyed on pointers and stream).
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        const void *in = nullptr;
+        void *out = nullptr;
+        hipStream_t stream = nullptr;
+    } graphs[4];
+
+    // Kernel timing.
+    static constexpr int kMaxTimed = 4096;
+    std::vector<hipEvent_t> ev_start, ev_stop;
+    std::vector<int> ev_kind;
+    int n_timed = 0;
+};
+
+// Element sizes.
+inline int grid_elem_bytes(int prec) { return prec == SHTX_FP64 ? 8 : 4; }
+
+// Kernel launchers (each checks its launch shape on the host first).
+hipError_t launch_gauss_nodes(int nlat, double *mu, double *w, hipStream_t s);
+hipError_t launch_legendre_tables(Plan &p, hipStream_t s);
+hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, hipStream_t s);
+hipError_t launch_gemm_direct(const Plan &p, const void *four, void *spec, bool adjoint,
+                              hipStream_t s);
+hipError_t launch_fft_c2r(const Plan &p, const void *four, void *grid, bool adjoint,
+                          hipStream_t s);
+hipError_t launch_fft_r2c(const Plan &p, const void *grid, void *four, bool adjoint,
+                          hipStream_t s);
+
+// GEMM tile sizes per precision (rows, columns) for each direction.
+void gemm_tiles(int prec, int *inv_bm, int *inv_bn, int *dir_bm, int *dir_bn);
+
+// Host-side Bluestein filter: out[k] = DFT_L(b)[k] / L in long double, b the
+// conjugate chirp wrapped to length L.
+void bluestein_filter(int h, int L, std::vector<long double> &re, std::vector<long double> &im);
+
+// Work lists are laid out as 8 equal segments, one per XCD (the hardware
+// deals workgroups to the 8 XCDs round-robin), padded with no-op items.
+// xcd_remap maps the hardware block index to the item index so that segment x
+// runs on XCD x in order: items that share data (the tiles of one m, the field
+// runs of one ring) are put in the same segment and share that XCD's L2.
+constexpr int kXcds = 8;
+
+__device__ inline int xcd_remap(int bid, int grid)
+{
+    int per = grid / kXcds;
+    return (bid % kXcds) * per + bid / kXcds;
+}
+
+// Host helper: place groups of items (each group kept on one XCD) into the 8
+// segments, heaviest group first onto the least-loaded segment, and pad.
+template <class Item>
+std::vector<Item> layout_by_xcd(const std::vector<std::vector<Item>> &groups,
+                                const std::vector<double> &cost, const Item &noop)
+{
+    std::vector<size_t> order(groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<std::vector<Item>> seg(kXcds);
+    double load[kXcds] = {0};
+    for (size_t g : order) {
+        int best = 0;
+        for (int x = 1; x < kXcds; ++x)
+            if (load[x] < load[best]) best = x;
+        load[best] += cost[g];
+        seg[best].insert(seg[best].end(), groups[g].begin(), groups[g].end());
+    }
+    size_t per = 0;
+    for (auto &v : seg) per = std::max(per, v.size());
+    if (per == 0) per = 1;
+    std::vector<Item> out(per * kXcds, noop);
+    for (int x = 0; x < kXcds; ++x)
+        std::copy(seg[x].begin(), seg[x].end(), out.begin() + x * per);
+    return out;
+}
+
+}  // namespace shtx

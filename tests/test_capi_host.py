@@ -1,0 +1,67 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+symbol, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "shtx.h")).read()
+    return sorted(set(re.findall(r"\b(shtx_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1908_06097_amd as shtx
+    if not os.path.exists(shtx.LIB_PATH):
+        pytest.fail("libshtx.so is not built (run __graft_entry__.build())")
+    return shtx.load_library()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "shtx_inv_trans" in names and "shtx_dir_trans_adj" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_strerror(lib):
+    assert lib.shtx_strerror(0) == b"success"
+    assert lib.shtx_strerror(-1) == b"invalid argument"
+    assert lib.shtx_strerror(-4) == b"unsupported configuration"
+
+
+@pytest.mark.parametrize("args,code", [
+    ((-1, 1, 64, 0, 1, 1), -1),        # negative truncation
+    ((31, 1, 64, 0, 0, 1), -1),        # no fields
+    ((31, 7, 64, 0, 1, 1), -1),        # unknown grid
+    ((31, 1, 64, 0, 1, 9), -1),        # unknown precision
+    ((31, 1, 63, 0, 1, 1), -4),        # odd number of latitudes
+    ((31, 0, 64, 127, 1, 1), -4),      # odd ring length on a full grid
+    ((31, 0, 64, 0, 1, 1), -1),        # full grid without a ring length
+])
+def test_plan_create_rejects_bad_arguments(lib, args, code):
+    h = ctypes.c_void_p()
+    rc = lib.shtx_plan_create(ctypes.byref(h), *args, 0, None)
+    assert rc == code
+    assert not h.value
+
+
+def test_null_handles(lib):
+    assert lib.shtx_plan_create(None, 31, 1, 64, 0, 1, 1, 0, None) == -1
+    assert lib.shtx_inv_trans(None, None, None, None) == -1
+    assert lib.shtx_plan_destroy(None) == -1
+    assert lib.shtx_plan_info(None, None) == -1
+
+
+def test_python_binding_refuses_without_gpu():
+    torch = pytest.importorskip("torch")
+    import paper_1908_06097_amd as shtx
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(shtx.ShtxError):
+        shtx.Plan(31, "octahedral", 64, 1, "fp32")

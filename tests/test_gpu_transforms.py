@@ -1,0 +1,203 @@
+"""GPU parity of the HIP transforms against the FP64 CPU oracle.
+
+Every call goes through the C ABI (via the thin Python binding).  Inputs are
+the seeded synthetic spectra of ``synth_inputs``; expected values come only
+from ``oracle``.  Tolerances: FP64 1e-12 (max relative), FP32 1e-5 (RMS),
+split BF16 1e-4 (RMS), per field, on spectral and grid outputs.
+"""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from metrics import grid_errors, spec_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL_RMS = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4}
+TOL_MAX = {"fp64": 1e-12, "fp32": 1e-4, "bf16x3": 1e-3}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test without a GPU")
+    return torch
+
+
+def _shtx():
+    import paper_1908_06097_amd as shtx
+    return shtx
+
+
+def _oracle():
+    import oracle
+    return oracle
+
+
+def _dev(x, dtype):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype).cuda()
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Plan-time data: nodes and tables
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nlat", [160, 512, 1280, 2560])
+def test_nodes_bitwise(nlat):
+    shtx, o = _shtx(), _oracle()
+    _say(f"nodes nlat={nlat}")
+    plan = shtx.Plan(15, "octahedral", nlat, 1, "fp64")
+    mu, w = plan.nodes()
+    mu_o, w_o = o.gauss(nlat)
+    assert np.array_equal(mu, mu_o), np.flatnonzero(mu != mu_o)[:10]
+    assert np.all(np.abs(w - w_o) <= np.spacing(w_o)), np.max(np.abs(w - w_o) / np.spacing(w_o))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-7), ("bf16x3", 1.5e-5)])
+def test_legendre_tables(prec, tol):
+    shtx, o = _shtx(), _oracle()
+    N, nlat = 255, 512
+    _say(f"tables T{N} O{nlat // 2} {prec}")
+    plan = shtx.Plan(N, "octahedral", nlat, 1, prec)
+    mu, _ = plan.nodes()
+    nlon = plan.ring_lengths()
+    for m in (0, 1, 17, 128, 200, 255):
+        tab = plan.legendre(m)
+        rings = [j for j in range(nlat // 2) if o.ring_cutoff(N, nlon[j]) >= m]
+        assert tab.shape == (len(rings), N - m + 1)
+        ref = o.legendre(N, m, mu[rings])
+        err = np.abs(tab - ref).max() / np.abs(ref).max()
+        assert err < tol, (m, err)
+
+
+# ---------------------------------------------------------------------------
+# Transforms on small and multi-tile shapes
+# ---------------------------------------------------------------------------
+
+def _check_all(plan, N, nlon, key, fields, prec):
+    torch, o = _torch(), _oracle()
+    mu, w = o.gauss(len(nlon))
+    a = si.spectral_fields(N, key, fields)
+    nf = len(fields)
+    g_ref = o.inv(N, nlon, a)
+    spec = _dev(a, plan.complex_dtype)
+    g = plan.inv(spec)
+    em, er = grid_errors(_np(g), g_ref, nlon, w)
+    _say(f"  inv   e_max {em.max():.2e} e_rms {er.max():.2e}")
+    assert er.max() < TOL_RMS[prec] and em.max() < TOL_MAX[prec]
+
+    b_ref = o.dir(N, nlon, g_ref)
+    b = plan.dir(_dev(g_ref, plan.real_dtype))
+    em, er = spec_errors(_np(b), b_ref, N)
+    _say(f"  dir   e_max {em.max():.2e} e_rms {er.max():.2e}")
+    assert er.max() < TOL_RMS[prec] and em.max() < TOL_MAX[prec]
+
+    y = np.stack([si.white_noise_grid(int(nlon.sum()), 500 + f) for f in range(nf)])
+    c_ref = o.inv_adj(N, nlon, y)
+    c = plan.inv_adj(_dev(y, plan.real_dtype))
+    em, er = spec_errors(_np(c), c_ref, N)
+    _say(f"  iadj  e_max {em.max():.2e} e_rms {er.max():.2e}")
+    assert er.max() < TOL_RMS[prec] and em.max() < TOL_MAX[prec]
+
+    d_ref = o.dir_adj(N, nlon, a)
+    d = plan.dir_adj(spec)
+    em, er = grid_errors(_np(d), d_ref, nlon, w)
+    _say(f"  dadj  e_max {em.max():.2e} e_rms {er.max():.2e}")
+    assert er.max() < TOL_RMS[prec] and em.max() < TOL_MAX[prec]
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("shape", ["T31_O32_F3", "T63_full_F2", "T159_O160_F70"])
+def test_transform_parity(prec, shape):
+    shtx, o = _shtx(), _oracle()
+    if shape == "T31_O32_F3":
+        N, grid, nlat, nl_full, F = 31, "octahedral", 64, 0, 3
+    elif shape == "T63_full_F2":
+        N, grid, nlat, nl_full, F = 63, "full", 64, 128, 2
+    else:
+        N, grid, nlat, nl_full, F = 159, "octahedral", 320, 0, 70
+    _say(f"parity {shape} {prec}")
+    plan = shtx.Plan(N, grid, nlat, F, prec, nlon_full=nl_full)
+    nlon = plan.ring_lengths()
+    _check_all(plan, N, nlon, 11, range(F), prec)
+
+
+def test_t79_full_fp64_round_trip():
+    """T79 on the full 160 x 320 grid, 1 field, FP64: parity and round trip <= 1e-12."""
+    shtx, o = _shtx(), _oracle()
+    wl = si.WORKLOADS["t79_full"]
+    plan = shtx.Plan(wl.trunc, "full", wl.nlat, 1, "fp64", nlon_full=wl.nlon_full)
+    nlon = plan.ring_lengths()
+    a = si.spectral_fields(wl.trunc, wl.key, [0])
+    _check_all(plan, wl.trunc, nlon, wl.key, [0], "fp64")
+    b = _np(plan.dir(plan.inv(_dev(a, plan.complex_dtype))))
+    em, er = spec_errors(b, a, wl.trunc)
+    _say(f"  round trip e_max {em.max():.2e} e_rms {er.max():.2e}")
+    assert em.max() < 1e-12 and er.max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Full-size workloads on sampled fields
+# ---------------------------------------------------------------------------
+
+def _full_size(key, prec, sample, check_dir=True):
+    torch, shtx, o = _torch(), _shtx(), _oracle()
+    wl = si.WORKLOADS[key]
+    _say(f"{wl.name} {prec}: F={wl.nfld}, sample {list(sample)}")
+    plan = shtx.Plan(wl.trunc, wl.grid, wl.nlat, wl.nfld, prec, nlon_full=wl.nlon_full)
+    nlon = plan.ring_lengths()
+    mu, w = o.gauss(wl.nlat)
+    a_all = si.spectral_fields(wl.trunc, wl.key, range(wl.nfld))
+    g = _np(plan.inv(_dev(a_all, plan.complex_dtype)))
+    a = a_all[list(sample)]
+    g_ref = o.inv(wl.trunc, nlon, a)
+    em, er = grid_errors(g[list(sample)], g_ref, nlon, w)
+    _say(f"  inv e_max {em.max():.2e} e_rms {er.max():.2e}")
+    assert er.max() < TOL_RMS[prec] and em.max() < TOL_MAX[prec]
+    if check_dir:
+        # direct transform of band-limited oracle grids in the sampled slots
+        g_in = np.repeat(g_ref[:1], wl.nfld, axis=0)
+        g_in[list(sample)] = g_ref
+        b = _np(plan.dir(_dev(g_in, plan.real_dtype)))
+        del g_in
+        b_ref = o.dir(wl.trunc, nlon, g_ref)
+        em, er = spec_errors(b[list(sample)], b_ref, wl.trunc)
+        _say(f"  dir e_max {em.max():.2e} e_rms {er.max():.2e}")
+        assert er.max() < TOL_RMS[prec] and em.max() < TOL_MAX[prec]
+        # round trip on the device, compared with the seeded input
+        b = _np(plan.dir(plan.inv(_dev(a_all, plan.complex_dtype))))
+        em, er = spec_errors(b[list(sample)], a, wl.trunc)
+        _say(f"  round trip vs input e_max {em.max():.2e} e_rms {er.max():.2e}")
+        assert er.max() < max(TOL_RMS[prec], 1e-12) * 4
+    plan.close()
+    torch.cuda.synchronize()
+
+
+def test_t255_o256_fp32_411_fields():
+    _full_size("t255_o256", "fp32", [0, 1, 137, 274, 410])
+
+
+def test_t255_o256_fp64_411_fields():
+    _full_size("t255_o256", "fp64", [0, 205, 410])
+
+
+def test_tco639_o640_bf16x3_411_fields():
+    _full_size("tco639_o640", "bf16x3", [0, 13, 26, 205, 410])
+
+
+def test_tco1279_o1280_fp32_411_fields():
+    _full_size("tco1279_o1280", "fp32", [0, 410], check_dir=True)
+
+
+def test_tco1279_o1280_bf16x3_411_fields():
+    _full_size("tco1279_o1280", "bf16x3", [205], check_dir=True)
