@@ -41,8 +41,9 @@ struct Acc<double> {
     typedef f64x4 type;
 };
 
-// 16x16x4 MFMA: lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
-// D[4(l/16)+v][l%16] for v = 0..3.
+// 16x16x4 MFMA: lane l supplies A[l%16][l/16] and B[l/16][l%16].  It holds
+// D[i][l%16] for v = 0..3 with i = 4(l/16) + v for the FP32 form and
+// i = l/16 + 4v for the FP64 form (the two differ on CDNA).
 __device__ inline f32x4 mfma16x16x4(float a, float b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -50,6 +51,12 @@ __device__ inline f32x4 mfma16x16x4(float a, float b, f32x4 c)
 __device__ inline f64x4 mfma16x16x4(double a, double b, f64x4 c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ inline int acc_row(int lane, int v)
+{
+    return sizeof(T) == 8 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
 }
 
 struct GemmArgs {
@@ -147,7 +154,7 @@ __global__ __launch_bounds__(256) void k_leg_inv_mfma(GemmArgs a)
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                int r = row0 + wr + i * 16 + 4 * (lane >> 4) + v;
+                int r = row0 + wr + i * 16 + acc_row<T>(lane, v);
                 int c = col0 + wc + j * 16 + (lane & 15);
                 if (r < b.R && c < ncol) {
                     T s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
@@ -238,7 +245,7 @@ __global__ __launch_bounds__(256) void k_leg_dir_mfma(GemmArgs a)
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    int k = row0 + wr + i * 16 + 4 * (lane >> 4) + v;
+                    int k = row0 + wr + i * 16 + acc_row<T>(lane, v);
                     int c = col0 + wc + j * 16 + (lane & 15);
                     int nrel = p + 2 * k;
                     if (m + nrel <= a.trunc && c < ncol) {

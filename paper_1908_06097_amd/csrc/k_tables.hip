@@ -15,7 +15,13 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // double-double arithmetic (hi + lo, |lo| <= ulp(hi) / 2)
+//
+// The error-free transformations below need every product rounded exactly
+// once where it is written: contracting a product into a later add (which the
+// GPU compiler does by default) makes the error terms inconsistent, so
+// contraction is off from here to the end of the node kernel.
 // ---------------------------------------------------------------------------
+#pragma clang fp contract(off)
 struct dd {
     double hi, lo;
 };
@@ -140,6 +146,8 @@ __global__ void k_gauss_nodes(int nlat, double *mu, double *w)
     mu[nlat - 1 - j] = -r.hi;
     w[nlat - 1 - j] = wq.hi;
 }
+
+#pragma clang fp contract(fast)
 
 // Sectoral seeds P̄_m^m(mu_j) = prod_{k<=m} sqrt((2k+1)/(2k)) s_j, one thread per
 // northern ring, s_j = sqrt((1 - mu_j)(1 + mu_j)).
