@@ -153,16 +153,30 @@ __device__ void stockham_pass(C2<T> *buf, int lbuf, int nf, int L, int Ns, const
     }
     __syncthreads();
     C2<T> wr[R];
+    if constexpr (R != 2 && R != 4 && R != 8) {
 #pragma unroll
-    for (int t = 0; t < R; ++t) wr[t] = W[t * (L / R)];
+        for (int t = 0; t < R; ++t) wr[t] = W[t * (L / R)];
+    }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         int e = threadIdx.x + b * kFftThreads;
         if (e < total) {
             int f = e / nbf, j = e - f * nbf;
             int k = j % Ns;
+            if (Ns > 1) {
+                // twiddles w^r, w = exp(-2 pi i k / (Ns R)), from one table
+                // load and products of w, w^2, w^4 (at most three deep)
+                C2<T> w1 = W[k * tstep];
+                C2<T> w2 = cmul(w1, w1);
+                C2<T> w4 = cmul(w2, w2);
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], W[k * r * tstep]);
+                for (int r = 1; r < R; ++r) {
+                    C2<T> t = (r & 1) ? w1 : C2<T>{T(1), T(0)};
+                    if (r & 2) t = (r & 1) ? cmul(t, w2) : w2;
+                    if (r & 4) t = (r & 3) ? cmul(t, w4) : w4;
+                    v[b][r] = cmul(v[b][r], t);
+                }
+            }
             dft_reg<T, R>(v[b], wr);
             int base = (j / Ns) * Ns * R + k;
 #pragma unroll
@@ -177,7 +191,7 @@ __device__ void fft_forward(C2<T> *buf, const RingDesc &d, int nf, const C2<T> *
 {
     int Ns = 1;
     for (int s = 0; s < d.nrad; ++s) {
-        int R = d.rad[s];
+        int R = (int)((d.radcode >> (4 * s)) & 15u);
         switch (R) {
         case 2: stockham_pass<T, 2, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
         case 3: stockham_pass<T, 3, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
@@ -340,7 +354,11 @@ bool check_fft(const Plan &p, int cap)
         if (d.grid_off + d.n > p.npts || d.four_off + (int64_t)(d.M + 1) * p.nfld > p.nfour * p.nfld)
             return false;
         int prod = 1;
-        for (int s = 0; s < d.nrad; ++s) prod *= d.rad[s];
+        for (int s = 0; s < d.nrad; ++s) {
+            int R = (int)((d.radcode >> (4 * s)) & 15u);
+            if (R != 2 && R != 3 && R != 4 && R != 5 && R != 7 && R != 8) return false;
+            prod *= R;
+        }
         if (prod != d.L) return false;
     }
     for (const FftItem &it : p.fft_items) {

@@ -64,7 +64,8 @@ struct GemmArgs {
     const void *tab_lo;  // split-BF16 lo half of the table
     const MBlock *mb;
     const GemmItem *items;
-    const RingDesc *rings;
+    const int64_t *four_off;  // per ring: first complex of its [m][nfld] block
+    const double *wq;         // per ring: Gauss weight
     const void *in;
     void *out;
     int trunc, nlat, nfld;
@@ -75,17 +76,38 @@ struct GemmArgs {
 __device__ inline int64_t spec_base(int trunc, int m) { return (int64_t)m * (2 * trunc + 3 - m) / 2; }
 
 // ---------------------------------------------------------------------------
-// FP64 / FP32: 2 x 2 waves, each owning a (BM/2) x (BN/2) tile per parity.
-// LDS tiles are K-major: As[p][kappa][i], Bs[p][kappa][j].
+// FP64 / FP32.  256 threads as 2 x 2 waves, each owning a (BM/2) x (BN/2)
+// tile per parity.  LDS tiles are K-major (As[buf][p][kappa][i],
+// Bs[buf][p][kappa][j]) and double-buffered: the global loads of stage s+1
+// are issued into registers before the MFMAs of stage s and written to the
+// other buffer after them, with one barrier per stage.
+//
+// INV: rows i = northern rings of the m band, kappa = k, A = table [p][k][r],
+//      B = spectral coefficients read straight from spec[f][index(m, n)].
+// DIR: rows i = k, kappa = rings, A = table [p][r][k], B = hemispheric
+//      fold of the Fourier workspace q_r (G_north +- G_south).
 // ---------------------------------------------------------------------------
-template <typename T, int BM, int BN, int BK>
-__global__ __launch_bounds__(256) void k_leg_inv_mfma(GemmArgs a)
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) Vec2 {
+    T x, y;
+};
+
+template <typename T, int BM, int BN, int BK, bool INV>
+__global__ __launch_bounds__(256) void k_leg_mfma(GemmArgs a)
 {
     constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
-    constexpr int LDA = BM + 4, LDB = BN + 4;
+    constexpr int LDA = BM + 16, LDB = BN + 16;
+    constexpr int VEC = 16 / sizeof(T);                 // elements per 16-byte table load
+    constexpr int NA = (2 * BK * BM) / (VEC * 256);     // table loads per thread per stage
+    // complex operand loads per thread per stage: INV reads BN/2 fields x 2 BK
+    // coefficients, DIR reads BK rings x BN/2 fields (north and south each)
+    constexpr int NB = INV ? (BK * BN) / 256 : (BK * BN) / 512;
+    static_assert(NA * VEC * 256 == 2 * BK * BM, "table tile must split evenly");
+    static_assert(NB * (INV ? 256 : 512) == BK * BN, "operand tile must split evenly");
     typedef typename Acc<T>::type V;
-    __shared__ T As[2][BK][LDA];
-    __shared__ T Bs[2][BK][LDB];
+    typedef T VecT __attribute__((ext_vector_type(VEC)));
+    __shared__ __attribute__((aligned(16))) T As[2][2][BK][LDA];
+    __shared__ __attribute__((aligned(16))) T Bs[2][2][BK][LDB];
 
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const GemmItem it = a.items[item];
@@ -96,126 +118,101 @@ __global__ __launch_bounds__(256) void k_leg_inv_mfma(GemmArgs a)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
     const int ncol = 2 * a.nfld;
-    const T *A0 = (const T *)a.tab + b.off_kr;
-    const T *A1 = A0 + (int64_t)b.Kp * b.Rp;
-    const T *spec = (const T *)a.in;
+    const int64_t pstride = (int64_t)b.Kp * b.Rp;
+    const T *A0 = (const T *)a.tab + (INV ? b.off_kr : b.off_rk);
+    const int lda_g = INV ? b.Rp : b.Kp;  // global row stride of the table tile
     const int64_t sb = spec_base(a.trunc, m);
+    const int kend = INV ? b.K0 : b.R;
+    const int nstages = (kend + BK - 1) / BK;
 
-    V acc[2][FM][FN];
-    for (int p = 0; p < 2; ++p)
-        for (int i = 0; i < FM; ++i)
-            for (int j = 0; j < FN; ++j) acc[p][i][j] = V{};
+    VecT ra[NA];
+    Vec2<T> rb0[NB], rb1[NB];
 
-    for (int kk = 0; kk < b.K0; kk += BK) {
-        // table tile: rows kappa = k, columns i = ring (contiguous in [p][k][r])
-        for (int e = tid; e < 2 * BK * BM; e += 256) {
-            int p = e / (BK * BM), rem = e - p * BK * BM, q = rem / BM, i = rem - q * BM;
-            const T *Ap = p ? A1 : A0;
-            As[p][q][i] = Ap[(int64_t)(kk + q) * b.Rp + row0 + i];
+    auto load = [&](int kk) {
+#pragma unroll
+        for (int v = 0; v < NA; ++v) {
+            int idx = tid + v * 256;
+            int p = idx / (BK * BM / VEC), rem = idx - p * (BK * BM / VEC);
+            int q = rem / (BM / VEC), i = (rem - q * (BM / VEC)) * VEC;
+            ra[v] = *reinterpret_cast<const VecT *>(A0 + p * pstride + (int64_t)(kk + q) * lda_g + row0 + i);
         }
-        // spectral tile: for each field, 2 BK consecutive n (both parities)
-        for (int e = tid; e < (BN / 2) * (2 * BK); e += 256) {
-            int fl = e / (2 * BK), t = e - fl * (2 * BK);
-            int f = col0 / 2 + fl, nrel = 2 * kk + t;
-            T re = 0, im = 0;
-            if (f < a.nfld && m + nrel <= a.trunc) {
-                int64_t o = 2 * ((int64_t)f * a.nspec + sb + nrel);
-                re = spec[o];
-                im = (m == 0) ? T(0) : spec[o + 1];
-            }
-            int p = t & 1, q = t >> 1;
-            Bs[p][q][2 * fl] = re;
-            Bs[p][q][2 * fl + 1] = im;
-        }
-        __syncthreads();
+        if (INV) {
+            const Vec2<T> *spec = (const Vec2<T> *)a.in;
 #pragma unroll
-        for (int q = 0; q < BK; q += 4) {
-            const int qq = q + (lane >> 4);
-#pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                T av[FM], bv[FN];
-#pragma unroll
-                for (int i = 0; i < FM; ++i) av[i] = As[p][qq][wr + i * 16 + (lane & 15)];
-#pragma unroll
-                for (int j = 0; j < FN; ++j) bv[j] = Bs[p][qq][wc + j * 16 + (lane & 15)];
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j) acc[p][i][j] = mfma16x16x4(av[i], bv[j], acc[p][i][j]);
-            }
-        }
-        __syncthreads();
-    }
-
-    T *four = (T *)a.out;
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-        for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int r = row0 + wr + i * 16 + acc_row<T>(lane, v);
-                int c = col0 + wc + j * 16 + (lane & 15);
-                if (r < b.R && c < ncol) {
-                    T s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
-                    int jn = b.j0 + r, js = a.nlat - 1 - jn;
-                    four[2 * (a.rings[jn].four_off + (int64_t)m * a.nfld) + c] = s0 + s1;
-                    four[2 * (a.rings[js].four_off + (int64_t)m * a.nfld) + c] = s0 - s1;
+            for (int v = 0; v < NB; ++v) {
+                int idx = tid + v * 256;
+                int fl = idx / (2 * BK), t = idx - fl * (2 * BK);
+                int f = col0 / 2 + fl, nrel = 2 * kk + t;
+                Vec2<T> z = {T(0), T(0)};
+                if (f < a.nfld && m + nrel <= a.trunc) {
+                    z = spec[(int64_t)f * a.nspec + sb + nrel];
+                    if (m == 0) z.y = T(0);
                 }
+                rb0[v] = z;
             }
-}
-
-template <typename T, int BM, int BN, int BK>
-__global__ __launch_bounds__(256) void k_leg_dir_mfma(GemmArgs a)
-{
-    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
-    constexpr int LDA = BM + 4, LDB = BN + 4;
-    typedef typename Acc<T>::type V;
-    __shared__ T As[2][BK][LDA];
-    __shared__ T Bs[2][BK][LDB];
-
-    const int item = xcd_remap(blockIdx.x, gridDim.x);
-    const GemmItem it = a.items[item];
-    if (it.m < 0) return;
-    const int m = it.m;
-    const MBlock b = a.mb[m];
-    const int row0 = it.tr * BM, col0 = it.tc * BN;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
-    const int ncol = 2 * a.nfld;
-    const T *A0 = (const T *)a.tab + b.off_rk;
-    const T *A1 = A0 + (int64_t)b.Rp * b.Kp;
-    const T *four = (const T *)a.in;
+        } else {
+            const Vec2<T> *four = (const Vec2<T> *)a.in;
+#pragma unroll
+            for (int v = 0; v < NB; ++v) {
+                int idx = tid + v * 256;
+                int q = idx / (BN / 2), cp = idx - q * (BN / 2);
+                int r = kk + q, f = col0 / 2 + cp;
+                Vec2<T> s0 = {T(0), T(0)}, s1 = {T(0), T(0)};
+                if (r < b.R && f < a.nfld) {
+                    int jn = b.j0 + r, js = a.nlat - 1 - jn;
+                    Vec2<T> gn = four[a.four_off[jn] + (int64_t)m * a.nfld + f];
+                    Vec2<T> gs = four[a.four_off[js] + (int64_t)m * a.nfld + f];
+                    T q_r = a.adjoint ? T(1) : T(0.5 * a.wq[jn]);
+                    s0 = {q_r * (gn.x + gs.x), q_r * (gn.y + gs.y)};
+                    s1 = {q_r * (gn.x - gs.x), q_r * (gn.y - gs.y)};
+                }
+                rb0[v] = s0;
+                rb1[v] = s1;
+            }
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int v = 0; v < NA; ++v) {
+            int idx = tid + v * 256;
+            int p = idx / (BK * BM / VEC), rem = idx - p * (BK * BM / VEC);
+            int q = rem / (BM / VEC), i = (rem - q * (BM / VEC)) * VEC;
+            *reinterpret_cast<VecT *>(&As[buf][p][q][i]) = ra[v];
+        }
+        if (INV) {
+#pragma unroll
+            for (int v = 0; v < NB; ++v) {
+                int idx = tid + v * 256;
+                int fl = idx / (2 * BK), t = idx - fl * (2 * BK);
+                int p = t & 1, q = t >> 1;
+                *reinterpret_cast<Vec2<T> *>(&Bs[buf][p][q][2 * fl]) = rb0[v];
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NB; ++v) {
+                int idx = tid + v * 256;
+                int q = idx / (BN / 2), cp = idx - q * (BN / 2);
+                *reinterpret_cast<Vec2<T> *>(&Bs[buf][0][q][2 * cp]) = rb0[v];
+                *reinterpret_cast<Vec2<T> *>(&Bs[buf][1][q][2 * cp]) = rb1[v];
+            }
+        }
+    };
 
     V acc[2][FM][FN];
+#pragma unroll
     for (int p = 0; p < 2; ++p)
+#pragma unroll
         for (int i = 0; i < FM; ++i)
+#pragma unroll
             for (int j = 0; j < FN; ++j) acc[p][i][j] = V{};
 
-    for (int rr = 0; rr < b.R; rr += BK) {
-        // table tile: rows kappa = ring, columns i = k (contiguous in [p][r][k])
-        for (int e = tid; e < 2 * BK * BM; e += 256) {
-            int p = e / (BK * BM), rem = e - p * BK * BM, q = rem / BM, i = rem - q * BM;
-            const T *Ap = p ? A1 : A0;
-            As[p][q][i] = Ap[(int64_t)(rr + q) * b.Kp + row0 + i];
-        }
-        // Fourier tile folded over the hemispheres
-        for (int e = tid; e < BK * BN; e += 256) {
-            int q = e / BN, cl = e - q * BN;
-            int r = rr + q, c = col0 + cl;
-            T b0 = 0, b1 = 0;
-            if (r < b.R && c < ncol) {
-                int jn = b.j0 + r, js = a.nlat - 1 - jn;
-                T gn = four[2 * (a.rings[jn].four_off + (int64_t)m * a.nfld) + c];
-                T gs = four[2 * (a.rings[js].four_off + (int64_t)m * a.nfld) + c];
-                T q_r = a.adjoint ? T(1) : T(0.5 * a.rings[jn].w);
-                b0 = q_r * (gn + gs);
-                b1 = q_r * (gn - gs);
-            }
-            Bs[0][q][cl] = b0;
-            Bs[1][q][cl] = b1;
-        }
-        __syncthreads();
+    load(0);
+    store(0);
+    __syncthreads();
+    for (int s = 0; s < nstages; ++s) {
+        const int cur = s & 1;
+        const bool more = s + 1 < nstages;
+        if (more) load((s + 1) * BK);
 #pragma unroll
         for (int q = 0; q < BK; q += 4) {
             const int qq = q + (lane >> 4);
@@ -223,37 +220,56 @@ __global__ __launch_bounds__(256) void k_leg_dir_mfma(GemmArgs a)
             for (int p = 0; p < 2; ++p) {
                 T av[FM], bv[FN];
 #pragma unroll
-                for (int i = 0; i < FM; ++i) av[i] = As[p][qq][wr + i * 16 + (lane & 15)];
+                for (int i = 0; i < FM; ++i) av[i] = As[cur][p][qq][wr + i * 16 + (lane & 15)];
 #pragma unroll
-                for (int j = 0; j < FN; ++j) bv[j] = Bs[p][qq][wc + j * 16 + (lane & 15)];
+                for (int j = 0; j < FN; ++j) bv[j] = Bs[cur][p][qq][wc + j * 16 + (lane & 15)];
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
                     for (int j = 0; j < FN; ++j) acc[p][i][j] = mfma16x16x4(av[i], bv[j], acc[p][i][j]);
             }
         }
+        if (more) store(cur ^ 1);
         __syncthreads();
     }
 
-    T *spec = (T *)a.out;
-    const int64_t sb = spec_base(a.trunc, m);
-#pragma unroll
-    for (int p = 0; p < 2; ++p)
+    if (INV) {
+        T *four = (T *)a.out;
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    int k = row0 + wr + i * 16 + acc_row<T>(lane, v);
+                    int r = row0 + wr + i * 16 + acc_row<T>(lane, v);
                     int c = col0 + wc + j * 16 + (lane & 15);
-                    int nrel = p + 2 * k;
-                    if (m + nrel <= a.trunc && c < ncol) {
-                        T val = acc[p][i][j][v];
-                        if (m == 0 && (c & 1)) val = 0;
-                        spec[2 * ((int64_t)(c >> 1) * a.nspec + sb + nrel) + (c & 1)] = val;
+                    if (r < b.R && c < ncol) {
+                        T s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
+                        int jn = b.j0 + r, js = a.nlat - 1 - jn;
+                        four[2 * (a.four_off[jn] + (int64_t)m * a.nfld) + c] = s0 + s1;
+                        four[2 * (a.four_off[js] + (int64_t)m * a.nfld) + c] = s0 - s1;
                     }
                 }
+    } else {
+        T *spec = (T *)a.out;
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int k = row0 + wr + i * 16 + acc_row<T>(lane, v);
+                        int c = col0 + wc + j * 16 + (lane & 15);
+                        int nrel = p + 2 * k;
+                        if (m + nrel <= a.trunc && c < ncol) {
+                            T val = acc[p][i][j][v];
+                            if (m == 0 && (c & 1)) val = 0;
+                            spec[2 * ((int64_t)(c >> 1) * a.nspec + sb + nrel) + (c & 1)] = val;
+                        }
+                    }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -353,9 +369,9 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
                 float b0 = 0.f, b1 = 0.f;
                 if (r < b.R && c < ncol) {
                     int jn = b.j0 + r, js = a.nlat - 1 - jn;
-                    float gn = four[2 * (a.rings[jn].four_off + (int64_t)m * a.nfld) + c];
-                    float gs = four[2 * (a.rings[js].four_off + (int64_t)m * a.nfld) + c];
-                    float q_r = a.adjoint ? 1.f : (float)(0.5 * a.rings[jn].w);
+                    float gn = four[2 * (a.four_off[jn] + (int64_t)m * a.nfld) + c];
+                    float gs = four[2 * (a.four_off[js] + (int64_t)m * a.nfld) + c];
+                    float q_r = a.adjoint ? 1.f : (float)(0.5 * a.wq[jn]);
                     b0 = q_r * (gn + gs);
                     b1 = q_r * (gn - gs);
                 }
@@ -403,8 +419,8 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
                     if (r < b.R && c < ncol) {
                         float s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
                         int jn = b.j0 + r, js = a.nlat - 1 - jn;
-                        four[2 * (a.rings[jn].four_off + (int64_t)m * a.nfld) + c] = (s0 + s1) * unscale;
-                        four[2 * (a.rings[js].four_off + (int64_t)m * a.nfld) + c] = (s0 - s1) * unscale;
+                        four[2 * (a.four_off[jn] + (int64_t)m * a.nfld) + c] = (s0 + s1) * unscale;
+                        four[2 * (a.four_off[js] + (int64_t)m * a.nfld) + c] = (s0 - s1) * unscale;
                     }
                 }
     } else {
@@ -434,7 +450,8 @@ GemmArgs make_args(const Plan &p, bool inverse_shape, const void *in, void *out,
     GemmArgs a{};
     a.mb = p.d_mb;
     a.items = inverse_shape ? p.d_inv_items : p.d_dir_items;
-    a.rings = p.d_rings;
+    a.four_off = p.d_ring_four_off;
+    a.wq = p.d_w;
     a.in = in;
     a.out = out;
     a.trunc = p.trunc;
@@ -485,10 +502,10 @@ hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, hipS
     if (grid == 0) return hipSuccess;
     if (p.prec == SHTX_FP64) {
         if (!check_items(p, p.inv_items, true, 64, 64, 16)) return hipErrorInvalidValue;
-        k_leg_inv_mfma<double, 64, 64, 16><<<grid, 256, 0, s>>>(a);
+        k_leg_mfma<double, 64, 64, 16, true><<<grid, 256, 0, s>>>(a);
     } else if (p.prec == SHTX_FP32) {
         if (!check_items(p, p.inv_items, true, 128, 128, 16)) return hipErrorInvalidValue;
-        k_leg_inv_mfma<float, 128, 128, 16><<<grid, 256, 0, s>>>(a);
+        k_leg_mfma<float, 128, 128, 16, true><<<grid, 256, 0, s>>>(a);
     } else {
         if (!check_items(p, p.inv_items, true, 128, 128, 32)) return hipErrorInvalidValue;
         k_leg_bf16x3<128, 128, 32, true><<<grid, 256, 0, s>>>(a);
@@ -502,10 +519,10 @@ hipError_t launch_gemm_direct(const Plan &p, const void *four, void *spec, bool 
     int grid = (int)p.dir_items.size();
     if (p.prec == SHTX_FP64) {
         if (!check_items(p, p.dir_items, false, 64, 64, 16)) return hipErrorInvalidValue;
-        k_leg_dir_mfma<double, 64, 64, 16><<<grid, 256, 0, s>>>(a);
+        k_leg_mfma<double, 64, 64, 16, false><<<grid, 256, 0, s>>>(a);
     } else if (p.prec == SHTX_FP32) {
         if (!check_items(p, p.dir_items, false, 128, 128, 16)) return hipErrorInvalidValue;
-        k_leg_dir_mfma<float, 128, 128, 16><<<grid, 256, 0, s>>>(a);
+        k_leg_mfma<float, 128, 128, 16, false><<<grid, 256, 0, s>>>(a);
     } else {
         if (!check_items(p, p.dir_items, false, 128, 128, 32)) return hipErrorInvalidValue;
         k_leg_bf16x3<128, 128, 32, false><<<grid, 256, 0, s>>>(a);

@@ -139,7 +139,7 @@ void free_plan(Plan &p)
 {
     void *ptrs[] = {p.d_mu, p.d_w, p.d_diag, p.d_tab_kr, p.d_tab_rk, p.d_tab_kr_lo,
                     p.d_tab_rk_lo, p.d_mmax, p.d_mb, p.d_inv_items, p.d_dir_items,
-                    p.d_rings, p.d_fft_items, p.d_twid, p.d_four};
+                    p.d_rings, p.d_ring_four_off, p.d_fft_items, p.d_twid, p.d_four};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &g : p.graphs)
@@ -270,8 +270,15 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
             lp.L = h;
             lp.blue = 0;
         } else {
+            // Bluestein length: the smallest 2^a 3^b >= 2h - 1 (radix-8/4/2/3
+            // passes only, the cheapest butterflies)
             int L = 2 * h - 1;
-            while (smooth_factor(L, f) != 1) ++L;
+            auto is23 = [](int x) {
+                while (x % 2 == 0) x /= 2;
+                while (x % 3 == 0) x /= 3;
+                return x == 1;
+            };
+            while (!is23(L)) ++L;
             lp.L = L;
             lp.blue = 1;
         }
@@ -337,7 +344,8 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
         d.L = lp.L;
         d.blue = lp.blue;
         d.nrad = (int)lp.rad.size();
-        for (int r = 0; r < d.nrad; ++r) d.rad[r] = lp.rad[r];
+        d.radcode = 0;
+        for (int r = 0; r < d.nrad; ++r) d.radcode |= (unsigned long long)lp.rad[r] << (4 * r);
         d.lbuf = std::max(d.L, d.h + 1);
         d.fb = std::max(1, std::min({F, cap / d.lbuf, 64}));
         d.tw_off = lp.tw;
@@ -361,6 +369,11 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
     p.fft_lds_bytes = lds_elems * (int)celem;
     p.fft_items = layout_by_xcd(fgroups, fcost, FftItem{-1, 0, 0, 0});
     PLAN_TRY(upload(&p.d_rings, p.rings));
+    {
+        std::vector<int64_t> fo(nlat);
+        for (int j = 0; j < nlat; ++j) fo[j] = p.rings[j].four_off;
+        PLAN_TRY(upload(&p.d_ring_four_off, fo));
+    }
     PLAN_TRY(upload(&p.d_fft_items, p.fft_items));
 
     // ---- GEMM work lists ----------------------------------------------------------

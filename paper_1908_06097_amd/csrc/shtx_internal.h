@@ -19,7 +19,7 @@ constexpr int kTablePad = 128;
 // Ring-FFT kernels hold at most this many complex values of one block in LDS.
 constexpr int kFftCapF32 = 8192;  // 64 KiB
 constexpr int kFftCapF64 = 6144;  // 96 KiB
-constexpr int kFftThreads = 256;
+constexpr int kFftThreads = 512;
 constexpr int kMaxRadices = 12;
 
 // One m block of the Legendre tables.
@@ -49,7 +49,7 @@ struct RingDesc {
     int blue;     // 1 if the length-h DFT goes through Bluestein's convolution
     int fb;       // fields per FFT block for this ring
     int lbuf;     // complex LDS slots per field: max(L, h + 1)
-    int rad[kMaxRadices];
+    unsigned long long radcode;  // radix of pass s in bits [4s, 4s + 4)
     int64_t tw_off;     // W_L[k] = exp(-2 pi i k / L), k < L
     int64_t post_off;   // exp(-2 pi i m / n), m <= h
     int64_t chirp_off;  // Bluestein chirp exp(-pi i k^2 / h), k < h
@@ -91,6 +91,7 @@ struct Plan {
     MBlock *d_mb = nullptr;
     GemmItem *d_inv_items = nullptr, *d_dir_items = nullptr;
     RingDesc *d_rings = nullptr;
+    int64_t *d_ring_four_off = nullptr;  // per ring: RingDesc::four_off
     FftItem *d_fft_items = nullptr;
     void *d_twid = nullptr;  // FFT twiddle pool (complex, grid precision)
     int64_t twid_elems = 0;  // complex entries in the pool
