@@ -1,0 +1,149 @@
+"""Runtime behaviour of the HIP transforms: hipGraph replay, determinism,
+exact scaling, field independence, NaN propagation, degenerate sizes and
+argument errors.  Every call goes through the C ABI."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+
+def _env():
+    import torch
+    import paper_1908_06097_amd as shtx
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test without a GPU")
+    return torch, shtx
+
+
+def _spec(torch, plan, key=21, fields=None):
+    fields = range(plan.nfld) if fields is None else fields
+    return torch.from_numpy(si.spectral_fields(plan.trunc, key, fields)).to(plan.complex_dtype).cuda()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+def test_graph_replay_matches_eager(prec):
+    torch, shtx = _env()
+    eager = shtx.Plan(63, "octahedral", 128, 5, prec)
+    graphed = shtx.Plan(63, "octahedral", 128, 5, prec, graph=True)
+    a = _spec(torch, eager)
+    ref_g = eager.inv(a)
+    ref_s = eager.dir(ref_g)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        a2 = a.clone()
+        g = torch.empty_like(ref_g)
+        s = torch.empty_like(ref_s)
+        for rep in range(4):
+            graphed.inv(a2, out=g)
+            graphed.dir(g, out=s)
+            side.synchronize()
+            assert torch.equal(g, ref_g), rep
+            assert torch.equal(s, ref_s), rep
+            g.mul_(0.5)  # eager work on the same stream between replays
+            s.zero_()
+    torch.cuda.synchronize()
+
+
+def test_bitwise_deterministic():
+    torch, shtx = _env()
+    plan = shtx.Plan(159, "octahedral", 320, 33, "fp32")
+    a = _spec(torch, plan)
+    g1, g2 = plan.inv(a), plan.inv(a)
+    assert torch.equal(g1, g2)
+    assert torch.equal(plan.dir(g1), plan.dir(g2))
+    assert torch.equal(plan.inv_adj(g1), plan.inv_adj(g2))
+    assert torch.equal(plan.dir_adj(a), plan.dir_adj(a))
+
+
+def test_power_of_two_scaling_is_exact_and_zero_maps_to_zero():
+    torch, shtx = _env()
+    plan = shtx.Plan(95, "octahedral", 192, 4, "fp32")
+    a = _spec(torch, plan)
+    assert torch.equal(plan.inv(2 * a), 2 * plan.inv(a))
+    g = plan.inv(a)
+    assert torch.equal(plan.dir(0.25 * g), 0.25 * plan.dir(g))
+    assert torch.count_nonzero(plan.inv(torch.zeros_like(a))) == 0
+    assert torch.count_nonzero(plan.dir(torch.zeros_like(g))) == 0
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_fields_are_independent(prec):
+    torch, shtx = _env()
+    plan = shtx.Plan(127, "octahedral", 256, 70, prec)
+    a = _spec(torch, plan)
+    b = a.clone()
+    b[1:] = 0
+    assert torch.equal(plan.inv(a)[0], plan.inv(b)[0])
+    g = plan.inv(a)
+    h = g.clone()
+    h[1:] = 0
+    assert torch.equal(plan.dir(g)[0], plan.dir(h)[0])
+
+
+def test_nan_propagates_only_within_its_field():
+    torch, shtx = _env()
+    plan = shtx.Plan(63, "octahedral", 128, 3, "fp32")
+    a = _spec(torch, plan)
+    a[1, 10] = float("nan")
+    g = plan.inv(a)
+    assert torch.isnan(g[1]).any()
+    assert not torch.isnan(g[0]).any() and not torch.isnan(g[2]).any()
+
+
+@pytest.mark.parametrize("trunc,grid,nlat,nlon", [(0, "octahedral", 2, 0), (1, "octahedral", 4, 0),
+                                                   (2, "full", 4, 6), (7, "full", 8, 16)])
+def test_degenerate_sizes_fp64(trunc, grid, nlat, nlon):
+    import oracle
+    torch, shtx = _env()
+    plan = shtx.Plan(trunc, grid, nlat, 2, "fp64", nlon_full=nlon)
+    nl = plan.ring_lengths()
+    a = si.spectral_fields(trunc, 31, [0, 1])
+    g = plan.inv(torch.from_numpy(a).cuda()).cpu().numpy()
+    ref = oracle.inv(trunc, nl, a)
+    assert np.max(np.abs(g - ref)) <= 1e-12 * np.max(np.abs(ref))
+    b = plan.dir(torch.from_numpy(ref).cuda()).cpu().numpy()
+    bref = oracle.dir(trunc, nl, ref)
+    assert np.max(np.abs(b - bref)) <= 1e-12 * np.max(np.abs(bref))
+
+
+def test_plan_info_and_geometry():
+    torch, shtx = _env()
+    plan = shtx.Plan(255, "octahedral", 512, 7, "fp32")
+    info = plan.info
+    assert info.nspec == 256 * 257 // 2
+    assert info.npts == int(plan.ring_lengths().sum()) == 271360
+    assert info.nfour == 100568
+    assert info.max_nlon == 1040 and info.table_bytes > 0 and info.legendre_flops > 0
+
+
+def test_argument_errors():
+    torch, shtx = _env()
+    plan = shtx.Plan(31, "octahedral", 64, 2, "fp32")
+    a = _spec(torch, plan)
+    with pytest.raises(shtx.ShtxError):
+        plan.inv(a.to(torch.complex128))
+    with pytest.raises(shtx.ShtxError):
+        plan.inv(a[:1])
+    with pytest.raises(shtx.ShtxError):
+        plan.inv(a.cpu())
+    lib = shtx.load_library()
+    buf = torch.zeros(max(plan.npts, 2 * plan.nspec) * 2, dtype=torch.float32, device="cuda")
+    p = ctypes.c_void_p(buf.data_ptr())
+    rc = lib.shtx_inv_trans(plan._h, p, p, None)  # output overlaps input
+    assert rc == -1
+    assert lib.shtx_plan_legendre(plan._h, 32, None) == -1
+
+
+def test_plan_create_destroy_cycles():
+    torch, shtx = _env()
+    free0, _ = torch.cuda.mem_get_info()
+    for _ in range(5):
+        p = shtx.Plan(255, "octahedral", 512, 16, "bf16x3")
+        p.close()
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 >= free0 - (64 << 20)
