@@ -95,6 +95,13 @@ int shtx_plan_create(shtx_plan *out, int trunc, int grid, int nlat, int nlon_ful
 
 int shtx_plan_info(shtx_plan p, shtx_info *out);
 
+/* Host-only dry run of shtx_plan_create: builds the plan's geometry, table
+ * layout, FFT length plans and work lists, checks every kernel's launch shape
+ * against them, and fills `out` (may be NULL; plan_seconds is 0) without
+ * touching any device.  Returns what shtx_plan_create would return for a
+ * shape problem (SHTX_EINVAL / SHTX_EUNSUPPORTED) or SHTX_OK. */
+int shtx_plan_check(int trunc, int grid, int nlat, int nlon_full, int nfld, int prec, shtx_info *out);
+
 /* Host copies of plan geometry: nlon[nlat] ring lengths. */
 int shtx_plan_ring_lengths(shtx_plan p, int32_t *nlon_host);
 

@@ -27,7 +27,7 @@ FLAG_TIMING = 2
 
 _lib = None
 
-_EXPORTS = ("shtx_plan_create", "shtx_plan_info", "shtx_plan_ring_lengths", "shtx_plan_nodes",
+_EXPORTS = ("shtx_plan_create", "shtx_plan_check", "shtx_plan_info", "shtx_plan_ring_lengths", "shtx_plan_nodes",
             "shtx_plan_legendre", "shtx_inv_trans", "shtx_dir_trans", "shtx_inv_trans_adj",
             "shtx_dir_trans_adj", "shtx_timing_reset", "shtx_timing_read", "shtx_plan_destroy",
             "shtx_strerror")
@@ -56,6 +56,7 @@ def load_library():
     vp, i32, u32 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint
     lib.shtx_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, i32, i32, u32, vp]
     lib.shtx_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
+    lib.shtx_plan_check.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.POINTER(Info)]
     lib.shtx_plan_ring_lengths.argtypes = [vp, ctypes.c_void_p]
     lib.shtx_plan_nodes.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
     lib.shtx_plan_legendre.argtypes = [vp, i32, ctypes.c_void_p]
@@ -71,6 +72,16 @@ def load_library():
             getattr(lib, name).restype = i32
     _lib = lib
     return lib
+
+
+def plan_check(trunc, grid="octahedral", nlat=None, nfld=1, prec="fp32", nlon_full=0):
+    """Host-only dry run of plan creation (no GPU): returns (status, Info)."""
+    lib = load_library()
+    if nlat is None:
+        nlat = 2 * (trunc + 1)
+    info = Info()
+    rc = lib.shtx_plan_check(trunc, GRIDS[grid], nlat, nlon_full, nfld, PRECS[prec], ctypes.byref(info))
+    return rc, info
 
 
 def _check(rc, what):

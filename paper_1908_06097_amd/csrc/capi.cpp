@@ -1,6 +1,8 @@
 // C ABI of libshtx (declared in include/shtx.h).  Argument checking, the
 // order of kernel launches per transform, optional hipGraph replay and the
 // per-kernel timing events; the arithmetic lives in the kernels.
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -24,6 +26,7 @@ int hip_status(hipError_t e)
 {
     if (e == hipSuccess) return SHTX_OK;
     (void)hipGetLastError();
+    if (std::getenv("SHTX_DEBUG")) std::fprintf(stderr, "shtx: HIP error %d: %s\n", (int)e, hipGetErrorString(e));
     return SHTX_EHIP;
 }
 
@@ -142,10 +145,8 @@ int shtx_plan_create(shtx_plan *out, int trunc, int grid, int nlat, int nlon_ful
     return SHTX_OK;
 }
 
-int shtx_plan_info(shtx_plan h, shtx_info *o)
+static void fill_info(const Plan &p, shtx_info *o)
 {
-    if (!h || !o) return SHTX_EINVAL;
-    const Plan &p = h->p;
     std::memset(o, 0, sizeof(*o));
     o->trunc = p.trunc;
     o->nlat = p.nlat;
@@ -160,6 +161,22 @@ int shtx_plan_info(shtx_plan h, shtx_info *o)
     o->workspace_bytes = p.workspace_bytes;
     o->legendre_flops = p.legendre_flops;
     o->plan_seconds = p.plan_seconds;
+}
+
+int shtx_plan_info(shtx_plan h, shtx_info *o)
+{
+    if (!h || !o) return SHTX_EINVAL;
+    fill_info(h->p, o);
+    return SHTX_OK;
+}
+
+int shtx_plan_check(int trunc, int grid, int nlat, int nlon_full, int nfld, int prec, shtx_info *out)
+{
+    Plan p;
+    int rc = shtx::plan_layout(p, trunc, grid, nlat, nlon_full, nfld, prec, 0);
+    if (rc != SHTX_OK) return rc;
+    if (!shtx::gemm_shapes_ok(p) || !shtx::fft_shapes_ok(p)) return SHTX_EUNSUPPORTED;
+    if (out) fill_info(p, out);
     return SHTX_OK;
 }
 

@@ -21,6 +21,9 @@
 //
 // The paper (Section 3.1.1) keeps fields resident on the device and packs on
 // the device; this kernel's layout and algorithm are this library's own.
+#include <cstdio>
+#include <cstdlib>
+
 #include "shtx_internal.h"
 
 namespace shtx {
@@ -134,21 +137,35 @@ __device__ inline void dft_reg(C2<T> *v, const C2<T> *wr)
     }
 }
 
-// One in-place Stockham pass of radix R over nf fields of length L in LDS.
+// floor(a / b) for 0 <= a < 2^24 and b >= 1 given rb = 1/b: (a + 1/2) / b is
+// at least 1/(2b) away from an integer, far more than the rounding error of
+// the double product, so the truncation is exact (no integer division).
+__device__ inline int fdiv(int a, double rb) { return (int)(((double)a + 0.5) * rb); }
+
+// LDS slot index with one pad entry per 8 complex values: the strided writes
+// of the first Stockham passes then spread over the banks.
+__device__ inline int pad(int i) { return i + (i >> 3); }
+
+// One in-place Stockham pass of radix R over nf fields of length L in LDS:
+// every thread reads all of its butterflies into registers, the block
+// synchronises, then each butterfly is twiddled, transformed and written.
 template <typename T, int R, int CAP>
-__device__ void stockham_pass(C2<T> *buf, int lbuf, int nf, int L, int Ns, const C2<T> *W)
+__device__ __attribute__((noinline)) void stockham_pass(C2<T> *buf, int lbufp, int nf, int L, int Ns,
+                                                        const C2<T> *W)
 {
     constexpr int NB = (CAP / R + kFftThreads - 1) / kFftThreads;
     const int nbf = L / R, total = nf * nbf;
     const int tstep = L / (Ns * R);
+    const double rnbf = 1.0 / nbf, rNs = 1.0 / Ns;
     C2<T> v[NB][R];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         int e = threadIdx.x + b * kFftThreads;
         if (e < total) {
-            int f = e / nbf, j = e - f * nbf;
+            int f = fdiv(e, rnbf), j = e - f * nbf;
+            const C2<T> *src = buf + f * lbufp;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = buf[f * lbuf + j + r * nbf];
+            for (int r = 0; r < R; ++r) v[b][r] = src[pad(j + r * nbf)];
         }
     }
     __syncthreads();
@@ -161,26 +178,32 @@ __device__ void stockham_pass(C2<T> *buf, int lbuf, int nf, int L, int Ns, const
     for (int b = 0; b < NB; ++b) {
         int e = threadIdx.x + b * kFftThreads;
         if (e < total) {
-            int f = e / nbf, j = e - f * nbf;
-            int k = j % Ns;
+            int f = fdiv(e, rnbf), j = e - f * nbf;
+            int q = fdiv(j, rNs), k = j - q * Ns;
             if (Ns > 1) {
-                // twiddles w^r, w = exp(-2 pi i k / (Ns R)), from one table
-                // load and products of w, w^2, w^4 (at most three deep)
-                C2<T> w1 = W[k * tstep];
-                C2<T> w2 = cmul(w1, w1);
-                C2<T> w4 = cmul(w2, w2);
+                if constexpr (R <= 8) {
+                    // twiddles w^r, w = exp(-2 pi i k / (Ns R)), from one table
+                    // load and products of w, w^2, w^4 (at most three deep)
+                    C2<T> w1 = W[k * tstep];
+                    C2<T> w2 = cmul(w1, w1);
+                    C2<T> w4 = cmul(w2, w2);
 #pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    C2<T> t = (r & 1) ? w1 : C2<T>{T(1), T(0)};
-                    if (r & 2) t = (r & 1) ? cmul(t, w2) : w2;
-                    if (r & 4) t = (r & 3) ? cmul(t, w4) : w4;
-                    v[b][r] = cmul(v[b][r], t);
+                    for (int r = 1; r < R; ++r) {
+                        C2<T> t = (r & 1) ? w1 : C2<T>{T(1), T(0)};
+                        if (r & 2) t = (r & 1) ? cmul(t, w2) : w2;
+                        if (r & 4) t = (r & 3) ? cmul(t, w4) : w4;
+                        v[b][r] = cmul(v[b][r], t);
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], W[k * r * tstep]);
                 }
             }
             dft_reg<T, R>(v[b], wr);
-            int base = (j / Ns) * Ns * R + k;
+            C2<T> *dst = buf + f * lbufp;
+            int base = q * Ns * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[f * lbuf + base + r * Ns] = v[b][r];
+            for (int r = 0; r < R; ++r) dst[pad(base + r * Ns)] = v[b][r];
         }
     }
     __syncthreads();
@@ -191,14 +214,16 @@ __device__ void fft_forward(C2<T> *buf, const RingDesc &d, int nf, const C2<T> *
 {
     int Ns = 1;
     for (int s = 0; s < d.nrad; ++s) {
-        int R = (int)((d.radcode >> (4 * s)) & 15u);
+        int R = (int)((d.radcode >> (5 * s)) & 31u);
         switch (R) {
-        case 2: stockham_pass<T, 2, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
-        case 3: stockham_pass<T, 3, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
-        case 4: stockham_pass<T, 4, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
-        case 5: stockham_pass<T, 5, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
-        case 7: stockham_pass<T, 7, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
-        default: stockham_pass<T, 8, CAP>(buf, d.lbuf, nf, d.L, Ns, W); break;
+        case 2: stockham_pass<T, 2, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
+        case 3: stockham_pass<T, 3, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
+        case 4: stockham_pass<T, 4, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
+        case 5: stockham_pass<T, 5, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
+        case 7: stockham_pass<T, 7, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
+        case 11: stockham_pass<T, 11, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
+        case 13: stockham_pass<T, 13, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
+        default: stockham_pass<T, 8, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
         }
         Ns *= R;
     }
@@ -214,9 +239,10 @@ __device__ void dft_h(C2<T> *buf, const RingDesc &d, int nf, const C2<T> *W, con
 {
     fft_forward<T, CAP>(buf, d, nf, W);
     if (d.blue) {
+        const double rL = 1.0 / d.L;
         for (int e = threadIdx.x; e < nf * d.L; e += kFftThreads) {
-            int f = e / d.L, k = e - f * d.L;
-            C2<T> *q = buf + f * d.lbuf + k;
+            int f = fdiv(e, rL), k = e - f * d.L;
+            C2<T> *q = buf + f * d.lbufp + pad(k);
             *q = cconj(cmul(*q, bhat[k]));
         }
         __syncthreads();
@@ -227,7 +253,7 @@ __device__ void dft_h(C2<T> *buf, const RingDesc &d, int nf, const C2<T> *W, con
 template <typename T>
 __device__ inline C2<T> dft_out(const C2<T> *slot, const RingDesc &d, const C2<T> *chirp, int k)
 {
-    return d.blue ? cmul(chirp[k], cconj(slot[k])) : slot[k];
+    return d.blue ? cmul(chirp[k], cconj(slot[pad(k)])) : slot[pad(k)];
 }
 
 template <typename T, int CAP>
@@ -242,14 +268,15 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_c2r(FftArgs a)
     const C2<T> *tw = (const C2<T> *)a.twid;
     const C2<T> *W = tw + d.tw_off, *post = tw + d.post_off;
     const C2<T> *chirp = tw + d.chirp_off, *bhat = tw + d.bhat_off;
-    const int nf = it.nf, f0 = it.f0, h = d.h, M = d.M, lbuf = d.lbuf;
+    const int nf = it.nf, f0 = it.f0, h = d.h, M = d.M, lbufp = d.lbufp;
     const C2<T> *four = (const C2<T> *)a.in + d.four_off;
     const T facpos = a.adjoint ? T(0.5) : T(1);
+    const double rnf = 1.0 / nf;
 
     // 1. kept coefficients Y_m (m <= M), zero up to index h (and to L for Bluestein)
     const int span = d.blue ? d.L : h + 1;
     for (int e = threadIdx.x; e < nf * span; e += kFftThreads) {
-        int m = e / nf, f = e - m * nf;
+        int m = fdiv(e, rnf), f = e - m * nf;
         C2<T> y = {T(0), T(0)};
         if (m <= M) {
             y = four[(int64_t)m * a.nfld + f0 + f];
@@ -258,16 +285,17 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_c2r(FftArgs a)
             else
                 y = {y.x * facpos, y.y * facpos};
         }
-        buf[f * lbuf + m] = y;
+        buf[f * lbufp + pad(m)] = y;
     }
     __syncthreads();
     // 2. merge into the length-h sequence u = conj(Z'), Z'_m = (Y_m + conj Y_{h-m})
     //    + i e^{2 pi i m / n} (Y_m - conj Y_{h-m}); Bluestein: times the chirp
     const int hp = h / 2 + 1;
+    const double rhp = 1.0 / hp;
     for (int e = threadIdx.x; e < nf * hp; e += kFftThreads) {
-        int f = e / hp, m = e - f * hp;
-        C2<T> *s = buf + f * lbuf;
-        C2<T> ym = s[m], yh = s[h - m];
+        int f = fdiv(e, rhp), m = e - f * hp;
+        C2<T> *s = buf + f * lbufp;
+        C2<T> ym = s[pad(m)], yh = s[pad(h - m)];
         auto zprime = [&](C2<T> a1, C2<T> a2, int mm) {
             C2<T> A = cadd(a1, cconj(a2)), B = csub(a1, cconj(a2));
             C2<T> t = cmul(cconj(post[mm]), B);
@@ -276,8 +304,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_c2r(FftArgs a)
             return d.blue ? cmul(u, chirp[mm]) : u;
         };
         C2<T> um = zprime(ym, yh, m);
-        if (m != 0 && m != h - m) s[h - m] = zprime(yh, ym, h - m);
-        s[m] = um;
+        if (m != 0 && m != h - m) s[pad(h - m)] = zprime(yh, ym, h - m);
+        s[pad(m)] = um;
     }
     __syncthreads();
     // 3. forward DFT of length h
@@ -285,9 +313,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_c2r(FftArgs a)
     // 4. z = conj(DFT(u)): even samples Re z, odd samples Im z
     const T scale = a.adjoint ? T(d.w / (2.0 * d.n)) : T(1);
     T *grid = (T *)a.out;
+    const double rh = 1.0 / h;
     for (int e = threadIdx.x; e < nf * h; e += kFftThreads) {
-        int f = e / h, k = e - f * h;
-        C2<T> r = dft_out(buf + f * lbuf, d, chirp, k);
+        int f = fdiv(e, rh), k = e - f * h;
+        C2<T> r = dft_out(buf + f * lbufp, d, chirp, k);
         C2<T> g = {scale * r.x, -scale * r.y};
         *reinterpret_cast<C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k) = g;
     }
@@ -305,28 +334,30 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_r2c(FftArgs a)
     const C2<T> *tw = (const C2<T> *)a.twid;
     const C2<T> *W = tw + d.tw_off, *post = tw + d.post_off;
     const C2<T> *chirp = tw + d.chirp_off, *bhat = tw + d.bhat_off;
-    const int nf = it.nf, f0 = it.f0, h = d.h, M = d.M, lbuf = d.lbuf;
+    const int nf = it.nf, f0 = it.f0, h = d.h, M = d.M, lbufp = d.lbufp;
     const T *grid = (const T *)a.in;
 
     // 1. z_k = g_{2k} + i g_{2k+1}; Bluestein: times the chirp, zero-padded to L
     const int span = d.blue ? d.L : h;
+    const double rspan = 1.0 / span;
     for (int e = threadIdx.x; e < nf * span; e += kFftThreads) {
-        int f = e / span, k = e - f * span;
+        int f = fdiv(e, rspan), k = e - f * span;
         C2<T> z = {T(0), T(0)};
         if (k < h) {
             z = *reinterpret_cast<const C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k);
             if (d.blue) z = cmul(z, chirp[k]);
         }
-        buf[f * lbuf + k] = z;
+        buf[f * lbufp + pad(k)] = z;
     }
     __syncthreads();
     dft_h<T, CAP>(buf, d, nf, W, bhat);
     // 3. split: Y_m = (Z_m + conj Z_{h-m}) / 2 - (i/2) e^{-2 pi i m / n} (Z_m - conj Z_{h-m})
     const T scale = a.adjoint ? T(1) : T(1.0 / d.n);
     C2<T> *four = (C2<T> *)a.out + d.four_off;
+    const double rnf = 1.0 / nf;
     for (int e = threadIdx.x; e < nf * (M + 1); e += kFftThreads) {
-        int m = e / nf, f = e - m * nf;
-        const C2<T> *s = buf + f * lbuf;
+        int m = fdiv(e, rnf), f = e - m * nf;
+        const C2<T> *s = buf + f * lbufp;
         C2<T> zm = dft_out(s, d, chirp, m);
         C2<T> zc = cconj(dft_out(s, d, chirp, m == 0 ? 0 : h - m));
         C2<T> A = cadd(zm, zc), B = csub(zm, zc);
@@ -341,52 +372,77 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_r2c(FftArgs a)
 template <typename T>
 bool check_fft(const Plan &p, int cap)
 {
-    if (p.fft_items.empty() || p.fft_items.size() % kXcds) return false;
+#define SHTX_FFT_FAIL                                                                    \
+    do {                                                                                 \
+        if (std::getenv("SHTX_DEBUG")) std::fprintf(stderr, "shtx: FFT check line %d\n", __LINE__); \
+        return false;                                                                    \
+    } while (0)
+    if (p.fft_items.empty() || p.fft_items.size() % kXcds) SHTX_FFT_FAIL;
     size_t celem = 2 * sizeof(T);
     for (const RingDesc &d : p.rings) {
-        if (d.lbuf > cap || d.L > d.lbuf || d.h + 1 > d.lbuf || d.M >= d.h) return false;
-        if ((size_t)d.fb * d.lbuf * celem > (size_t)p.fft_lds_bytes) return false;
-        if (d.tw_off < 0 || d.tw_off + d.L > p.twid_elems) return false;
-        if (d.post_off < 0 || d.post_off + d.h + 1 > p.twid_elems) return false;
+        if (d.lbuf > cap || d.L > d.lbuf || d.h + 1 > d.lbuf || d.M >= d.h) SHTX_FFT_FAIL;
+        if (d.lbufp < d.lbuf + (d.lbuf - 1) / 8 + 1) SHTX_FFT_FAIL;  // pad(lbuf - 1) < lbufp
+        if ((size_t)d.fb * d.lbufp * celem > (size_t)p.fft_lds_bytes) SHTX_FFT_FAIL;
+        if (d.tw_off < 0 || d.tw_off + d.L > p.twid_elems) SHTX_FFT_FAIL;
+        if (d.post_off < 0 || d.post_off + d.h + 1 > p.twid_elems) SHTX_FFT_FAIL;
         if (d.blue && (d.chirp_off < 0 || d.chirp_off + d.h > p.twid_elems || d.bhat_off < 0 ||
                        d.bhat_off + d.L > p.twid_elems))
-            return false;
+            SHTX_FFT_FAIL;
         if (d.grid_off + d.n > p.npts || d.four_off + (int64_t)(d.M + 1) * p.nfld > p.nfour * p.nfld)
-            return false;
+            SHTX_FFT_FAIL;
         int prod = 1;
         for (int s = 0; s < d.nrad; ++s) {
-            int R = (int)((d.radcode >> (4 * s)) & 15u);
-            if (R != 2 && R != 3 && R != 4 && R != 5 && R != 7 && R != 8) return false;
+            int R = (int)((d.radcode >> (5 * s)) & 31u);
+            bool ok = R == 4 || R == 8;
+            for (int q : {2, 3, 5, 7, 11, 13}) ok = ok || R == q;
+            if (!ok) SHTX_FFT_FAIL;
             prod *= R;
         }
-        if (prod != d.L) return false;
+        if (prod != d.L) SHTX_FFT_FAIL;
     }
     for (const FftItem &it : p.fft_items) {
         if (it.ring < 0) continue;
-        if (it.ring >= p.nlat || it.f0 < 0 || it.nf < 1 || it.f0 + it.nf > p.nfld) return false;
-        if (it.nf > p.rings[it.ring].fb) return false;
+        if (it.ring >= p.nlat || it.f0 < 0 || it.nf < 1 || it.f0 + it.nf > p.nfld) SHTX_FFT_FAIL;
+        if (it.nf > p.rings[it.ring].fb) SHTX_FFT_FAIL;
     }
     return true;
+#undef SHTX_FFT_FAIL
 }
 
 template <typename T, int CAP, bool C2R>
 hipError_t launch_fft(const Plan &p, const void *in, void *out, bool adjoint, hipStream_t s)
 {
-    if (!check_fft<T>(p, CAP)) return hipErrorInvalidValue;
+    if (!check_fft<T>(p, CAP)) {
+        if (std::getenv("SHTX_DEBUG")) std::fprintf(stderr, "shtx: ring-FFT launch shape check failed\n");
+        return hipErrorInvalidValue;
+    }
     FftArgs a{p.d_rings, p.d_fft_items, p.d_twid, in, out, p.nfld, adjoint ? 1 : 0, p.npts};
     auto kern = C2R ? k_fft_c2r<T, CAP> : k_fft_r2c<T, CAP>;
-    static bool attr_set = false;
-    if (!attr_set) {
+    // raise the kernel's dynamic-LDS limit when a plan needs more than any
+    // earlier one (above 64 KiB it must be requested explicitly)
+    static int attr_bytes = 0;
+    if (p.fft_lds_bytes > attr_bytes) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, CAP * (int)sizeof(C2<T>));
-        if (e != hipSuccess) return e;
-        attr_set = true;
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, p.fft_lds_bytes);
+        if (e != hipSuccess) {
+            if (std::getenv("SHTX_DEBUG"))
+                std::fprintf(stderr, "shtx: dynamic LDS limit %d bytes refused\n", p.fft_lds_bytes);
+            return e;
+        }
+        attr_bytes = p.fft_lds_bytes;
     }
     kern<<<(int)p.fft_items.size(), kFftThreads, p.fft_lds_bytes, s>>>(a);
     return hipGetLastError();
 }
 
 }  // namespace
+
+bool fft_shapes_ok(const Plan &p)
+{
+    bool ok = p.prec == SHTX_FP64 ? check_fft<double>(p, kFftCapF64) : check_fft<float>(p, kFftCapF32);
+    if (!ok && std::getenv("SHTX_DEBUG")) std::fprintf(stderr, "shtx: ring-FFT launch shape check failed\n");
+    return ok;
+}
 
 hipError_t launch_fft_c2r(const Plan &p, const void *four, void *grid, bool adjoint, hipStream_t s)
 {

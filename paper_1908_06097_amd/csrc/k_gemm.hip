@@ -20,6 +20,9 @@
 // The paper treats this step only as part of the SH dwarf (Section 3.1.1);
 // the design (grouped launch, XCD-aware work lists, LDS-staged tiles, MFMA)
 // is this library's own.
+#include <cstdio>
+#include <cstdlib>
+
 #include "shtx_internal.h"
 
 namespace shtx {
@@ -29,6 +32,7 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct Acc;
@@ -292,18 +296,19 @@ __device__ inline void split_bf16(float x, unsigned short &hi, unsigned short &l
     lo = bf16_rne(x - bf16_to_f(hi));
 }
 
-__device__ inline f32x4 mfma_bf16(const unsigned short *pa, const unsigned short *pb, f32x4 c)
-{
-    bf16x8 av = *reinterpret_cast<const bf16x8 *>(pa);
-    bf16x8 bv = *reinterpret_cast<const bf16x8 *>(pb);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
-}
 
 template <int BM, int BN, int BK, bool INVERSE>
 __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
 {
     constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
     constexpr int LDK = BK + 8;  // 16-byte aligned rows, staggered banks
+    constexpr int CH = BK / 8;   // 16-byte chunks per tile row
+    constexpr int NA = (2 * 2 * BM * CH) / 256;  // table chunk loads per thread
+    // operand units per thread: INV (field, parity, 8 consecutive k),
+    // DIR (field, 8 consecutive rings)
+    constexpr int NU = INVERSE ? (BN / 2) * 2 * (BK / 8) / 256 : (BN / 2) * (BK / 8) / 256;
+    static_assert(NA * 256 == 2 * 2 * BM * CH, "table tile must split evenly");
+    static_assert(NU >= 1, "operand tile too small");
     __shared__ __attribute__((aligned(16))) unsigned short As[2][2][BM][LDK];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[2][2][BN][LDK];
 
@@ -324,83 +329,174 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
     const unsigned short *Th = (const unsigned short *)a.tab + off;
     const unsigned short *Tl = (const unsigned short *)a.tab_lo + off;
     const int kend = INVERSE ? b.K0 : b.R;
+    const int nstages = (kend + BK - 1) / BK;
 
-    f32x4 acc[2][FM][FN];
-    for (int p = 0; p < 2; ++p)
-        for (int i = 0; i < FM; ++i)
-            for (int j = 0; j < FN; ++j) acc[p][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    u32x4 ra[NA];
+    float2 rv[NU][INVERSE ? 8 : 16];
 
-    for (int kk = 0; kk < kend; kk += BK) {
-        // table tile: 2 parities x 2 halves x BM rows x BK kappa, 8 per 16-byte load
-        constexpr int CH = BK / 8;
-        for (int e = tid; e < 2 * 2 * BM * CH; e += 256) {
-            int p = e / (2 * BM * CH), rem = e - p * 2 * BM * CH;
+    auto load = [&](int kk) __attribute__((always_inline)) {
+#pragma unroll
+        for (int v = 0; v < NA; ++v) {
+            int idx = tid + v * 256;
+            int p = idx / (2 * BM * CH), rem = idx - p * 2 * BM * CH;
             int hl = rem / (BM * CH);
             rem -= hl * BM * CH;
             int i = rem / CH, ch = rem - i * CH;
-            const unsigned short *src = (hl ? Tl : Th) + p * pstride + (int64_t)(row0 + i) * lda + kk + ch * 8;
-            *reinterpret_cast<uint4 *>(&As[p][hl][i][ch * 8]) = *reinterpret_cast<const uint4 *>(src);
+            ra[v] = *reinterpret_cast<const u32x4 *>((hl ? Tl : Th) + p * pstride + (int64_t)(row0 + i) * lda + kk + ch * 8);
         }
-        if (INVERSE) {
-            const float *spec = (const float *)a.in;
-            for (int e = tid; e < (BN / 2) * (2 * BK); e += 256) {
-                int fl = e / (2 * BK), t = e - fl * (2 * BK);
-                int f = col0 / 2 + fl, nrel = 2 * kk + t;
-                float re = 0.f, im = 0.f;
-                if (f < a.nfld && m + nrel <= a.trunc) {
-                    int64_t o = 2 * ((int64_t)f * a.nspec + sb + nrel);
-                    re = spec[o];
-                    im = (m == 0) ? 0.f : spec[o + 1];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            int idx = tid + u * 256;
+            if (INVERSE) {
+                // 8 consecutive k of one parity of one field: n = m + 2(kk + q) + p
+                int fl = idx / (2 * (BK / 8)), rem = idx - fl * 2 * (BK / 8);
+                int p = rem & 1, qc = rem >> 1;
+                int f = col0 / 2 + fl;
+                const float2 *spec = (const float2 *)a.in + (int64_t)f * a.nspec + sb;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    int nrel = 2 * (kk + qc * 8 + q) + p;
+                    float2 z = {0.f, 0.f};
+                    if (f < a.nfld && m + nrel <= a.trunc) {
+                        z = spec[nrel];
+                        if (m == 0) z.y = 0.f;
+                    }
+                    rv[u][q] = z;
                 }
-                int p = t & 1, q = t >> 1;
-                unsigned short h, l;
-                split_bf16(re, h, l);
-                Bs[p][0][2 * fl][q] = h;
-                Bs[p][1][2 * fl][q] = l;
-                split_bf16(im, h, l);
-                Bs[p][0][2 * fl + 1][q] = h;
-                Bs[p][1][2 * fl + 1][q] = l;
-            }
-        } else {
-            const float *four = (const float *)a.in;
-            for (int e = tid; e < BK * BN; e += 256) {
-                int q = e / BN, cl = e - q * BN;
-                int r = kk + q, c = col0 + cl;
-                float b0 = 0.f, b1 = 0.f;
-                if (r < b.R && c < ncol) {
-                    int jn = b.j0 + r, js = a.nlat - 1 - jn;
-                    float gn = four[2 * (a.four_off[jn] + (int64_t)m * a.nfld) + c];
-                    float gs = four[2 * (a.four_off[js] + (int64_t)m * a.nfld) + c];
-                    float q_r = a.adjoint ? 1.f : (float)(0.5 * a.wq[jn]);
-                    b0 = q_r * (gn + gs);
-                    b1 = q_r * (gn - gs);
+            } else {
+                // 8 consecutive rings of one field, north and south
+                int rc = idx / (BN / 2), cp = idx - rc * (BN / 2);
+                int f = col0 / 2 + cp;
+                const float2 *four = (const float2 *)a.in;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    int r = kk + rc * 8 + q;
+                    float2 gn = {0.f, 0.f}, gs = {0.f, 0.f};
+                    if (r < b.R && f < a.nfld) {
+                        int jn = b.j0 + r, js = a.nlat - 1 - jn;
+                        gn = four[a.four_off[jn] + (int64_t)m * a.nfld + f];
+                        gs = four[a.four_off[js] + (int64_t)m * a.nfld + f];
+                        float q_r = a.adjoint ? 1.f : (float)(0.5 * a.wq[jn]);
+                        gn.x *= q_r;
+                        gn.y *= q_r;
+                        gs.x *= q_r;
+                        gs.y *= q_r;
+                    }
+                    rv[u][2 * q] = gn;
+                    rv[u][2 * q + 1] = gs;
                 }
-                unsigned short h, l;
-                split_bf16(b0, h, l);
-                Bs[0][0][cl][q] = h;
-                Bs[0][1][cl][q] = l;
-                split_bf16(b1, h, l);
-                Bs[1][0][cl][q] = h;
-                Bs[1][1][cl][q] = l;
             }
         }
+    };
+    // pack 8 floats into (hi, lo) bf16 halves, one 16-byte word each
+    auto pack2 = [](float x0, float x1, unsigned &hi, unsigned &lo) {
+        unsigned short h0, l0, h1, l1;
+        split_bf16(x0, h0, l0);
+        split_bf16(x1, h1, l1);
+        hi = h0 | (unsigned)h1 << 16;
+        lo = l0 | (unsigned)l1 << 16;
+    };
+    auto split8 = [&](float x0, float x1, float x2, float x3, float x4, float x5, float x6, float x7,
+                      u32x4 &hi, u32x4 &lo) {
+        unsigned h0, l0, h1, l1, h2, l2, h3, l3;
+        pack2(x0, x1, h0, l0);
+        pack2(x2, x3, h1, l1);
+        pack2(x4, x5, h2, l2);
+        pack2(x6, x7, h3, l3);
+        hi = u32x4{h0, h1, h2, h3};
+        lo = u32x4{l0, l1, l2, l3};
+    };
+    auto store = [&]() __attribute__((always_inline)) {
+#pragma unroll
+        for (int v = 0; v < NA; ++v) {
+            int idx = tid + v * 256;
+            int p = idx / (2 * BM * CH), rem = idx - p * 2 * BM * CH;
+            int hl = rem / (BM * CH);
+            rem -= hl * BM * CH;
+            int i = rem / CH, ch = rem - i * CH;
+            *reinterpret_cast<u32x4 *>(&As[p][hl][i][ch * 8]) = ra[v];
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            int idx = tid + u * 256;
+            u32x4 hi, lo;
+            if (INVERSE) {
+                int fl = idx / (2 * (BK / 8)), rem = idx - fl * 2 * (BK / 8);
+                int p = rem & 1, qc = rem >> 1;
+#define z rv[u]
+                split8(z[0].x, z[1].x, z[2].x, z[3].x, z[4].x, z[5].x, z[6].x, z[7].x, hi, lo);
+                *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * fl][qc * 8]) = hi;
+                *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * fl][qc * 8]) = lo;
+                split8(z[0].y, z[1].y, z[2].y, z[3].y, z[4].y, z[5].y, z[6].y, z[7].y, hi, lo);
+                *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * fl + 1][qc * 8]) = hi;
+                *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * fl + 1][qc * 8]) = lo;
+#undef z
+            } else {
+                int rc = idx / (BN / 2), cp = idx - rc * (BN / 2);
+#define z rv[u]  // z[2q] north, z[2q+1] south of ring q
+#define SHTX_FOLD(c, sgn)                                                                         \
+    split8(z[0].c sgn z[1].c, z[2].c sgn z[3].c, z[4].c sgn z[5].c, z[6].c sgn z[7].c,              \
+           z[8].c sgn z[9].c, z[10].c sgn z[11].c, z[12].c sgn z[13].c, z[14].c sgn z[15].c, hi, lo)
+                SHTX_FOLD(x, +);
+                *reinterpret_cast<u32x4 *>(&Bs[0][0][2 * cp][rc * 8]) = hi;
+                *reinterpret_cast<u32x4 *>(&Bs[0][1][2 * cp][rc * 8]) = lo;
+                SHTX_FOLD(y, +);
+                *reinterpret_cast<u32x4 *>(&Bs[0][0][2 * cp + 1][rc * 8]) = hi;
+                *reinterpret_cast<u32x4 *>(&Bs[0][1][2 * cp + 1][rc * 8]) = lo;
+                SHTX_FOLD(x, -);
+                *reinterpret_cast<u32x4 *>(&Bs[1][0][2 * cp][rc * 8]) = hi;
+                *reinterpret_cast<u32x4 *>(&Bs[1][1][2 * cp][rc * 8]) = lo;
+                SHTX_FOLD(y, -);
+                *reinterpret_cast<u32x4 *>(&Bs[1][0][2 * cp + 1][rc * 8]) = hi;
+                *reinterpret_cast<u32x4 *>(&Bs[1][1][2 * cp + 1][rc * 8]) = lo;
+#undef SHTX_FOLD
+#undef z
+            }
+        }
+    };
+
+    f32x4 acc[2][FM][FN];
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j) acc[p][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    load(0);
+    for (int s = 0; s < nstages; ++s) {
+        store();
         __syncthreads();
+        if (s + 1 < nstages) load((s + 1) * BK);  // in flight during the MFMAs
 #pragma unroll
         for (int q = 0; q < BK; q += 32) {
             const int kq = q + 8 * (lane >> 4);
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
+            for (int p = 0; p < 2; ++p) {
+                bf16x8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const int ai = wr + i * 16 + (lane & 15);
+                    ah[i] = *reinterpret_cast<const bf16x8 *>(&As[p][0][ai][kq]);
+                    al[i] = *reinterpret_cast<const bf16x8 *>(&As[p][1][ai][kq]);
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const int bj = wc + j * 16 + (lane & 15);
+                    bh[j] = *reinterpret_cast<const bf16x8 *>(&Bs[p][0][bj][kq]);
+                    bl[j] = *reinterpret_cast<const bf16x8 *>(&Bs[p][1][bj][kq]);
+                }
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
                     for (int j = 0; j < FN; ++j) {
-                        const int ai = wr + i * 16 + (lane & 15), bj = wc + j * 16 + (lane & 15);
                         f32x4 c = acc[p][i][j];
-                        c = mfma_bf16(&As[p][0][ai][kq], &Bs[p][1][bj][kq], c);
-                        c = mfma_bf16(&As[p][1][ai][kq], &Bs[p][0][bj][kq], c);
-                        c = mfma_bf16(&As[p][0][ai][kq], &Bs[p][0][bj][kq], c);
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], c, 0, 0, 0);
+                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], c, 0, 0, 0);
                         acc[p][i][j] = c;
                     }
+            }
         }
         __syncthreads();
     }
@@ -471,8 +567,19 @@ GemmArgs make_args(const Plan &p, bool inverse_shape, const void *in, void *out,
 
 // Host check that every tile of a work list reads and writes inside the
 // table, Fourier and spectral arrays for the given tile sizes.
-bool check_items(const Plan &p, const std::vector<GemmItem> &items, bool inverse_shape, int bm, int bn,
-                 int bk)
+bool check_items_impl(const Plan &p, const std::vector<GemmItem> &items, bool inverse_shape, int bm, int bn,
+                      int bk);
+
+bool check_items(const Plan &p, const std::vector<GemmItem> &items, bool inverse_shape, int bm, int bn, int bk)
+{
+    bool ok = check_items_impl(p, items, inverse_shape, bm, bn, bk);
+    if (!ok && std::getenv("SHTX_DEBUG"))
+        std::fprintf(stderr, "shtx: Legendre GEMM work-list check failed (%s)\n", inverse_shape ? "inverse" : "direct");
+    return ok;
+}
+
+bool check_items_impl(const Plan &p, const std::vector<GemmItem> &items, bool inverse_shape, int bm, int bn,
+                      int bk)
 {
     if (items.empty() || items.size() % kXcds) return false;
     int ncol = 2 * p.nfld;
@@ -494,6 +601,15 @@ bool check_items(const Plan &p, const std::vector<GemmItem> &items, bool inverse
 }
 
 }  // namespace
+
+bool gemm_shapes_ok(const Plan &p)
+{
+    int bk = p.prec == SHTX_BF16X3 ? 32 : 16;
+    int bm = p.prec == SHTX_FP64 ? 64 : 128, bn = bm;
+    if (p.inv_bm != bm || p.inv_bn != bn || p.dir_bm != bm || p.dir_bn != bn) return false;
+    bool inv_ok = p.inv_items.empty() || check_items(p, p.inv_items, true, bm, bn, bk);
+    return inv_ok && check_items(p, p.dir_items, false, bm, bn, bk);
+}
 
 hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, hipStream_t s)
 {

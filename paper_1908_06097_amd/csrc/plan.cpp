@@ -26,11 +26,15 @@ int ring_cutoff(int trunc, int nlon)
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
-// Factor n over {2, 3, 5, 7}; returns the unfactored remainder.
+// Radices the ring-FFT kernel implements directly (primes; 4 and 8 are
+// formed from the factors of 2).
+const int kPrimeRadices[] = {2, 3, 5, 7, 11, 13};
+
+// Factor n over the direct prime radices; returns the unfactored remainder.
 int smooth_factor(int n, std::vector<int> &f)
 {
     f.clear();
-    for (int p : {2, 3, 5, 7})
+    for (int p : kPrimeRadices)
         while (n % p == 0) {
             f.push_back(p);
             n /= p;
@@ -38,8 +42,9 @@ int smooth_factor(int n, std::vector<int> &f)
     return n;
 }
 
-// Stockham radices for a 7-smooth length: as many radix-8 passes as the
-// power of two allows, then a 4 or 2, then the odd primes.
+// Stockham radices for a smooth length: the odd primes first, largest first
+// (the first pass needs no twiddles, so the costliest butterflies go there),
+// then as many radix-8 passes as the power of two allows, then a 4 or 2.
 std::vector<int> radices_for(int L)
 {
     std::vector<int> f;
@@ -52,11 +57,11 @@ std::vector<int> radices_for(int L)
         else
             odd.push_back(p);
     }
-    std::vector<int> r;
+    std::sort(odd.rbegin(), odd.rend());
+    std::vector<int> r(odd.begin(), odd.end());
     for (; twos >= 3; twos -= 3) r.push_back(8);
     if (twos == 2) r.push_back(4);
     if (twos == 1) r.push_back(2);
-    r.insert(r.end(), odd.begin(), odd.end());
     return r;
 }
 
@@ -158,10 +163,11 @@ void free_plan(Plan &p)
         }                                                \
     } while (0)
 
-int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, int prec,
-               unsigned flags, hipStream_t stream)
+// Host part of plan construction: geometry, table layout, FFT length plans
+// and twiddle tables (kept on the host until uploaded), GEMM and FFT work
+// lists.  Touches no device state, so it can be checked on any machine.
+int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, int prec, unsigned flags)
 {
-    auto t0 = std::chrono::steady_clock::now();
     if (trunc < 0 || nfld < 1 || nlat < 2) return SHTX_EINVAL;
     if (grid != SHTX_GRID_FULL && grid != SHTX_GRID_OCTAHEDRAL) return SHTX_EINVAL;
     if (prec != SHTX_FP64 && prec != SHTX_FP32 && prec != SHTX_BF16X3) return SHTX_EINVAL;
@@ -220,34 +226,8 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
     p.tab_elems = off;
     p.legendre_flops = flops;
 
-    // ---- Gauss nodes and Legendre tables (device, FP64) ---------------------
-    PLAN_TRY(hipMalloc(&p.d_mu, sizeof(double) * nlat));
-    PLAN_TRY(hipMalloc(&p.d_w, sizeof(double) * nlat));
-    PLAN_TRY(launch_gauss_nodes(nlat, p.d_mu, p.d_w, stream));
-
     size_t tab_el = prec == SHTX_FP64 ? 8 : prec == SHTX_FP32 ? 4 : 2;
-    PLAN_TRY(hipMalloc(&p.d_tab_kr, tab_el * p.tab_elems));
-    PLAN_TRY(hipMalloc(&p.d_tab_rk, tab_el * p.tab_elems));
-    p.table_bytes = 2 * tab_el * p.tab_elems;
-    if (prec == SHTX_BF16X3) {
-        PLAN_TRY(hipMalloc(&p.d_tab_kr_lo, tab_el * p.tab_elems));
-        PLAN_TRY(hipMalloc(&p.d_tab_rk_lo, tab_el * p.tab_elems));
-        p.table_bytes *= 2;
-    }
-    PLAN_TRY(hipMalloc(&p.d_diag, sizeof(double) * (size_t)NL * (N + 1)));
-    PLAN_TRY(hipMalloc(&p.d_mmax, sizeof(unsigned long long) * (N + 1)));
-    PLAN_TRY(upload(&p.d_mb, p.mb));
-    PLAN_TRY(launch_legendre_tables(p, stream));
-    PLAN_TRY(hipStreamSynchronize(stream));
-    // exponents were decided on the device; refresh the host copy
-    PLAN_TRY(hipMemcpy(p.mb.data(), p.d_mb, sizeof(MBlock) * p.mb.size(), hipMemcpyDeviceToHost));
-    (void)hipFree(p.d_diag);
-    p.d_diag = nullptr;
-    (void)hipFree(p.d_mmax);
-    p.d_mmax = nullptr;
-
-    std::vector<double> w(nlat);
-    PLAN_TRY(hipMemcpy(w.data(), p.d_w, sizeof(double) * nlat, hipMemcpyDeviceToHost));
+    p.table_bytes = (prec == SHTX_BF16X3 ? 4 : 2) * tab_el * p.tab_elems;
 
     // ---- ring FFT plans and twiddle pool --------------------------------------
     const bool dbl = prec == SHTX_FP64;
@@ -315,20 +295,9 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
         lens[n] = lp;
     }
     size_t celem = dbl ? 16 : 8;
-    {
-        p.twid_elems = (int64_t)pool.size() / 2;
-        size_t bytes = pool.size() / 2 * celem;
-        PLAN_TRY(hipMalloc(&p.d_twid, bytes));
-        if (dbl) {
-            std::vector<double> host(pool.begin(), pool.end());
-            PLAN_TRY(hipMemcpy(p.d_twid, host.data(), bytes, hipMemcpyHostToDevice));
-        } else {
-            std::vector<float> host(pool.size());
-            for (size_t i = 0; i < pool.size(); ++i) host[i] = (float)pool[i];
-            PLAN_TRY(hipMemcpy(p.d_twid, host.data(), bytes, hipMemcpyHostToDevice));
-        }
-        p.workspace_bytes += bytes;
-    }
+    p.twid_elems = (int64_t)pool.size() / 2;
+    p.twid_host.assign(pool.begin(), pool.end());
+    p.workspace_bytes += (size_t)p.twid_elems * celem;
 
     p.rings.resize(nlat);
     int64_t goff = 0, foff = 0;
@@ -345,20 +314,21 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
         d.blue = lp.blue;
         d.nrad = (int)lp.rad.size();
         d.radcode = 0;
-        for (int r = 0; r < d.nrad; ++r) d.radcode |= (unsigned long long)lp.rad[r] << (4 * r);
+        for (int r = 0; r < d.nrad; ++r) d.radcode |= (unsigned long long)lp.rad[r] << (5 * r);
         d.lbuf = std::max(d.L, d.h + 1);
-        d.fb = std::max(1, std::min({F, cap / d.lbuf, 64}));
+        d.lbufp = d.lbuf + d.lbuf / 8 + 1;
+        d.fb = std::max(1, std::min(F, cap / d.lbuf));
         d.tw_off = lp.tw;
         d.post_off = lp.post;
         d.chirp_off = lp.chirp;
         d.bhat_off = lp.bhat;
         d.grid_off = goff;
         d.four_off = foff;
-        d.w = w[j];
+        d.w = 0.0;  // filled in once the device has computed the weights
         goff += d.n;
         foff += (int64_t)(d.M + 1) * F;
         p.rings[j] = d;
-        lds_elems = std::max(lds_elems, d.fb * d.lbuf);
+        lds_elems = std::max(lds_elems, d.fb * d.lbufp);
         std::vector<FftItem> g;
         for (int f0 = 0; f0 < F; f0 += d.fb) g.push_back(FftItem{j, f0, std::min(d.fb, F - f0), 0});
         fgroups.push_back(g);
@@ -367,14 +337,9 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
     p.npts = goff;
     p.nfour = foff / F;
     p.fft_lds_bytes = lds_elems * (int)celem;
+    p.fft_lds_max = lds_elems;
+    if (p.fft_lds_bytes > 160 * 1024) return SHTX_EUNSUPPORTED;
     p.fft_items = layout_by_xcd(fgroups, fcost, FftItem{-1, 0, 0, 0});
-    PLAN_TRY(upload(&p.d_rings, p.rings));
-    {
-        std::vector<int64_t> fo(nlat);
-        for (int j = 0; j < nlat; ++j) fo[j] = p.rings[j].four_off;
-        PLAN_TRY(upload(&p.d_ring_four_off, fo));
-    }
-    PLAN_TRY(upload(&p.d_fft_items, p.fft_items));
 
     // ---- GEMM work lists ----------------------------------------------------------
     gemm_tiles(prec, &p.inv_bm, &p.inv_bn, &p.dir_bm, &p.dir_bn);
@@ -405,13 +370,78 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
         p.inv_items = layout_by_xcd(gi, ci, GemmItem{-1, 0, 0, 0});
         p.dir_items = layout_by_xcd(gd, cd, GemmItem{-1, 0, 0, 0});
     }
+
+    p.workspace_bytes += (size_t)p.nfour * F * celem;
+    return SHTX_OK;
+}
+
+// Full plan: host layout, then the device work (nodes, weights, tables,
+// uploads, workspace) on `stream`.
+int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, int prec,
+               unsigned flags, hipStream_t stream)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = plan_layout(p, trunc, grid, nlat, nlon_full, nfld, prec, flags);
+    if (rc != SHTX_OK) return rc;
+    if (!gemm_shapes_ok(p) || !fft_shapes_ok(p)) return SHTX_EUNSUPPORTED;
+    const int N = trunc, NL = nlat / 2;
+
+    // ---- Gauss nodes and Legendre tables (device, FP64) ---------------------
+    PLAN_TRY(hipMalloc(&p.d_mu, sizeof(double) * nlat));
+    PLAN_TRY(hipMalloc(&p.d_w, sizeof(double) * nlat));
+    PLAN_TRY(launch_gauss_nodes(nlat, p.d_mu, p.d_w, stream));
+
+    size_t tab_el = prec == SHTX_FP64 ? 8 : prec == SHTX_FP32 ? 4 : 2;
+    PLAN_TRY(hipMalloc(&p.d_tab_kr, tab_el * p.tab_elems));
+    PLAN_TRY(hipMalloc(&p.d_tab_rk, tab_el * p.tab_elems));
+    p.table_bytes = 2 * tab_el * p.tab_elems;
+    if (prec == SHTX_BF16X3) {
+        PLAN_TRY(hipMalloc(&p.d_tab_kr_lo, tab_el * p.tab_elems));
+        PLAN_TRY(hipMalloc(&p.d_tab_rk_lo, tab_el * p.tab_elems));
+        p.table_bytes *= 2;
+    }
+    PLAN_TRY(hipMalloc(&p.d_diag, sizeof(double) * (size_t)NL * (N + 1)));
+    PLAN_TRY(hipMalloc(&p.d_mmax, sizeof(unsigned long long) * (N + 1)));
+    PLAN_TRY(upload(&p.d_mb, p.mb));
+    PLAN_TRY(launch_legendre_tables(p, stream));
+    PLAN_TRY(hipStreamSynchronize(stream));
+    // exponents were decided on the device; refresh the host copy
+    PLAN_TRY(hipMemcpy(p.mb.data(), p.d_mb, sizeof(MBlock) * p.mb.size(), hipMemcpyDeviceToHost));
+    (void)hipFree(p.d_diag);
+    p.d_diag = nullptr;
+    (void)hipFree(p.d_mmax);
+    p.d_mmax = nullptr;
+
+
+    std::vector<double> w(nlat);
+    PLAN_TRY(hipMemcpy(w.data(), p.d_w, sizeof(double) * nlat, hipMemcpyDeviceToHost));
+    for (int j = 0; j < nlat; ++j) p.rings[j].w = w[j];
+
+    const bool dbl = prec == SHTX_FP64;
+    size_t celem = dbl ? 16 : 8;
+    {
+        size_t bytes = (size_t)p.twid_elems * celem;
+        PLAN_TRY(hipMalloc(&p.d_twid, bytes));
+        if (dbl) {
+            PLAN_TRY(hipMemcpy(p.d_twid, p.twid_host.data(), bytes, hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> host(p.twid_host.size());
+            for (size_t i = 0; i < host.size(); ++i) host[i] = (float)p.twid_host[i];
+            PLAN_TRY(hipMemcpy(p.d_twid, host.data(), bytes, hipMemcpyHostToDevice));
+        }
+        std::vector<double>().swap(p.twid_host);
+    }
+    PLAN_TRY(upload(&p.d_rings, p.rings));
+    {
+        std::vector<int64_t> fo(nlat);
+        for (int j = 0; j < nlat; ++j) fo[j] = p.rings[j].four_off;
+        PLAN_TRY(upload(&p.d_ring_four_off, fo));
+    }
+    PLAN_TRY(upload(&p.d_fft_items, p.fft_items));
     PLAN_TRY(upload(&p.d_inv_items, p.inv_items));
     PLAN_TRY(upload(&p.d_dir_items, p.dir_items));
 
-    // ---- Fourier workspace ---------------------------------------------------------
-    size_t four_bytes = (size_t)p.nfour * F * celem;
-    PLAN_TRY(hipMalloc(&p.d_four, four_bytes));
-    p.workspace_bytes += four_bytes;
+    PLAN_TRY(hipMalloc(&p.d_four, (size_t)p.nfour * nfld * celem));
 
     if (flags & SHTX_FLAG_TIMING) {
         p.ev_start.resize(Plan::kMaxTimed);

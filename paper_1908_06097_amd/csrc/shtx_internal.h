@@ -19,7 +19,7 @@ constexpr int kTablePad = 128;
 // Ring-FFT kernels hold at most this many complex values of one block in LDS.
 constexpr int kFftCapF32 = 8192;  // 64 KiB
 constexpr int kFftCapF64 = 6144;  // 96 KiB
-constexpr int kFftThreads = 512;
+constexpr int kFftThreads = 1024;
 constexpr int kMaxRadices = 12;
 
 // One m block of the Legendre tables.
@@ -48,8 +48,9 @@ struct RingDesc {
     int nrad;     // number of Stockham passes
     int blue;     // 1 if the length-h DFT goes through Bluestein's convolution
     int fb;       // fields per FFT block for this ring
-    int lbuf;     // complex LDS slots per field: max(L, h + 1)
-    unsigned long long radcode;  // radix of pass s in bits [4s, 4s + 4)
+    int lbuf;     // complex values per field slot: max(L, h + 1)
+    int lbufp;    // LDS entries per field slot with one pad per 8 values
+    unsigned long long radcode;  // radix of pass s in bits [5s, 5s + 5)
     int64_t tw_off;     // W_L[k] = exp(-2 pi i k / L), k < L
     int64_t post_off;   // exp(-2 pi i m / n), m <= h
     int64_t chirp_off;  // Bluestein chirp exp(-pi i k^2 / h), k < h
@@ -81,6 +82,7 @@ struct Plan {
     std::vector<GemmItem> inv_items, dir_items;
     std::vector<FftItem> fft_items;
     int fft_lds_bytes = 0;
+    int fft_lds_max = 0;  // complex entries of LDS the largest FFT block may use
 
     // Device memory.
     double *d_mu = nullptr, *d_w = nullptr;  // nlat
@@ -95,6 +97,7 @@ struct Plan {
     FftItem *d_fft_items = nullptr;
     void *d_twid = nullptr;  // FFT twiddle pool (complex, grid precision)
     int64_t twid_elems = 0;  // complex entries in the pool
+    std::vector<double> twid_host;  // pool (re, im) before upload
     void *d_four = nullptr;  // Fourier workspace [ring][m][nfld] complex
     int64_t tab_elems = 0;   // elements per table layout
     size_t table_bytes = 0, workspace_bytes = 0;
@@ -129,6 +132,12 @@ hipError_t launch_fft_c2r(const Plan &p, const void *four, void *grid, bool adjo
                           hipStream_t s);
 hipError_t launch_fft_r2c(const Plan &p, const void *grid, void *four, bool adjoint,
                           hipStream_t s);
+
+// Host checks that every kernel's work list and launch shape stay inside the
+// plan's arrays and the kernels' compile-time limits (no device access).
+bool gemm_shapes_ok(const Plan &p);
+bool fft_shapes_ok(const Plan &p);
+int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, int prec, unsigned flags);
 
 // GEMM tile sizes per precision (rows, columns) for each direction.
 void gemm_tiles(int prec, int *inv_bm, int *inv_bn, int *dir_bm, int *dir_bn);

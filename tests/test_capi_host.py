@@ -65,3 +65,28 @@ def test_python_binding_refuses_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(shtx.ShtxError):
         shtx.Plan(31, "octahedral", 64, 1, "fp32")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_plan_check_all_workloads(lib, prec):
+    """Host dry run of every workload's plan: geometry and every kernel's
+    launch shape pass the library's own bounds checks, without a GPU."""
+    import paper_1908_06097_amd as shtx
+    import synth_inputs as si
+    sizes = {"t79_full": (3240, 51200, 12800), "t255_o256": (32896, 271360, 100568),
+             "t399_o400": (80200, 654400, 243560), "tco639_o640": (205120, 1661440, 620120),
+             "tco1279_o1280": (819840, 6599680, 2469080)}
+    for key, w in si.WORKLOADS.items():
+        if key == "tco1279_o1280" and prec != "fp32":
+            continue  # same layout code; keep the CPU suite short
+        rc, info = shtx.plan_check(w.trunc, w.grid, w.nlat, w.nfld, prec, w.nlon_full)
+        assert rc == 0, (key, prec, rc)
+        assert (info.nspec, info.npts, info.nfour) == sizes[key]
+        assert info.table_bytes > 0 and info.legendre_flops > 0
+
+
+def test_plan_check_rejects(lib):
+    import paper_1908_06097_amd as shtx
+    assert shtx.plan_check(31, "octahedral", 63)[0] == -4
+    assert shtx.plan_check(-1, "octahedral", 64)[0] == -1
+    assert shtx.plan_check(31, "full", 64, nlon_full=0)[0] == -1
