@@ -62,6 +62,11 @@ __device__ inline C2<T> cmi(C2<T> a)
     return {a.y, -a.x};
 }
 
+// Dynamic LDS of the FFT kernels, declared once at namespace scope so that the
+// non-inlined pass functions address it as LDS (ds_* instructions) rather
+// than through generic pointers.
+extern __shared__ __attribute__((aligned(16))) unsigned char fft_smem[];
+
 struct FftArgs {
     const RingDesc *rings;
     const FftItem *items;
@@ -149,10 +154,12 @@ __device__ inline int pad(int i) { return i + (i >> 3); }
 // One in-place Stockham pass of radix R over nf fields of length L in LDS:
 // every thread reads all of its butterflies into registers, the block
 // synchronises, then each butterfly is twiddled, transformed and written.
-template <typename T, int R, int CAP>
-__device__ __attribute__((noinline)) void stockham_pass(C2<T> *buf, int lbufp, int nf, int L, int Ns,
-                                                        const C2<T> *W)
+template <typename T, int R, int CAP, bool TWL>
+__device__ __attribute__((noinline)) void stockham_pass(int buf_off, int lbufp, int nf, int L, int Ns,
+                                                        const C2<T> *Wg)
 {
+    C2<T> *buf = reinterpret_cast<C2<T> *>(fft_smem) + buf_off;
+    const C2<T> *W = TWL ? reinterpret_cast<const C2<T> *>(fft_smem) : Wg;
     constexpr int NB = (CAP / R + kFftThreads - 1) / kFftThreads;
     const int nbf = L / R, total = nf * nbf;
     const int tstep = L / (Ns * R);
@@ -209,21 +216,21 @@ __device__ __attribute__((noinline)) void stockham_pass(C2<T> *buf, int lbufp, i
     __syncthreads();
 }
 
-template <typename T, int CAP>
-__device__ void fft_forward(C2<T> *buf, const RingDesc &d, int nf, const C2<T> *W)
+template <typename T, int CAP, bool TWL>
+__device__ void fft_forward(int buf_off, const RingDesc &d, int nf, const C2<T> *W)
 {
     int Ns = 1;
     for (int s = 0; s < d.nrad; ++s) {
         int R = (int)((d.radcode >> (5 * s)) & 31u);
         switch (R) {
-        case 2: stockham_pass<T, 2, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
-        case 3: stockham_pass<T, 3, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
-        case 4: stockham_pass<T, 4, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
-        case 5: stockham_pass<T, 5, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
-        case 7: stockham_pass<T, 7, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
-        case 11: stockham_pass<T, 11, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
-        case 13: stockham_pass<T, 13, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
-        default: stockham_pass<T, 8, CAP>(buf, d.lbufp, nf, d.L, Ns, W); break;
+        case 2: stockham_pass<T, 2, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
+        case 3: stockham_pass<T, 3, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
+        case 4: stockham_pass<T, 4, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
+        case 5: stockham_pass<T, 5, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
+        case 7: stockham_pass<T, 7, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
+        case 11: stockham_pass<T, 11, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
+        case 13: stockham_pass<T, 13, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
+        default: stockham_pass<T, 8, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
         }
         Ns *= R;
     }
@@ -234,10 +241,11 @@ __device__ void fft_forward(C2<T> *buf, const RingDesc &d, int nf, const C2<T> *
 // multiplied by the chirp and zero-padded to L; the result is left as
 // conj(conv) and the caller multiplies by the chirp when reading (see
 // dft_out below).
-template <typename T, int CAP>
-__device__ void dft_h(C2<T> *buf, const RingDesc &d, int nf, const C2<T> *W, const C2<T> *bhat)
+template <typename T, int CAP, bool TWL>
+__device__ void dft_h(int buf_off, const RingDesc &d, int nf, const C2<T> *W, const C2<T> *bhat)
 {
-    fft_forward<T, CAP>(buf, d, nf, W);
+    C2<T> *buf = reinterpret_cast<C2<T> *>(fft_smem) + buf_off;
+    fft_forward<T, CAP, TWL>(buf_off, d, nf, W);
     if (d.blue) {
         const double rL = 1.0 / d.L;
         for (int e = threadIdx.x; e < nf * d.L; e += kFftThreads) {
@@ -246,7 +254,7 @@ __device__ void dft_h(C2<T> *buf, const RingDesc &d, int nf, const C2<T> *W, con
             *q = cconj(cmul(*q, bhat[k]));
         }
         __syncthreads();
-        fft_forward<T, CAP>(buf, d, nf, W);
+        fft_forward<T, CAP, TWL>(buf_off, d, nf, W);
     }
 }
 
@@ -256,22 +264,29 @@ __device__ inline C2<T> dft_out(const C2<T> *slot, const RingDesc &d, const C2<T
     return d.blue ? cmul(chirp[k], cconj(slot[pad(k)])) : slot[pad(k)];
 }
 
-template <typename T, int CAP>
+template <typename T, int CAP, bool TWL>
 __global__ __launch_bounds__(kFftThreads) void k_fft_c2r(FftArgs a)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *buf = reinterpret_cast<C2<T> *>(fft_smem);
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const FftItem it = a.items[item];
     if (it.ring < 0) return;
     const RingDesc d = a.rings[it.ring];
     const C2<T> *tw = (const C2<T> *)a.twid;
-    const C2<T> *W = tw + d.tw_off, *post = tw + d.post_off;
+    const C2<T> *W = tw + d.tw_off;
+    const C2<T> *post = tw + d.post_off;
     const C2<T> *chirp = tw + d.chirp_off, *bhat = tw + d.bhat_off;
     const int nf = it.nf, f0 = it.f0, h = d.h, M = d.M, lbufp = d.lbufp;
     const C2<T> *four = (const C2<T> *)a.in + d.four_off;
     const T facpos = a.adjoint ? T(0.5) : T(1);
     const double rnf = 1.0 / nf;
+    int buf_off = 0;
+    if (TWL) {
+        // the length-L twiddle table goes to LDS ahead of the field slots
+        for (int k = threadIdx.x; k < d.L; k += kFftThreads) buf[k] = W[k];
+        buf_off = d.L;
+        buf += d.L;
+    }
 
     // 1. kept coefficients Y_m (m <= M), zero up to index h (and to L for Bluestein)
     const int span = d.blue ? d.L : h + 1;
@@ -309,7 +324,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_c2r(FftArgs a)
     }
     __syncthreads();
     // 3. forward DFT of length h
-    dft_h<T, CAP>(buf, d, nf, W, bhat);
+    dft_h<T, CAP, TWL>(buf_off, d, nf, W, bhat);
     // 4. z = conj(DFT(u)): even samples Re z, odd samples Im z
     const T scale = a.adjoint ? T(d.w / (2.0 * d.n)) : T(1);
     T *grid = (T *)a.out;
@@ -322,20 +337,26 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_c2r(FftArgs a)
     }
 }
 
-template <typename T, int CAP>
+template <typename T, int CAP, bool TWL>
 __global__ __launch_bounds__(kFftThreads) void k_fft_r2c(FftArgs a)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    C2<T> *buf = reinterpret_cast<C2<T> *>(smem);
+    C2<T> *buf = reinterpret_cast<C2<T> *>(fft_smem);
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const FftItem it = a.items[item];
     if (it.ring < 0) return;
     const RingDesc d = a.rings[it.ring];
     const C2<T> *tw = (const C2<T> *)a.twid;
-    const C2<T> *W = tw + d.tw_off, *post = tw + d.post_off;
+    const C2<T> *W = tw + d.tw_off;
+    const C2<T> *post = tw + d.post_off;
     const C2<T> *chirp = tw + d.chirp_off, *bhat = tw + d.bhat_off;
     const int nf = it.nf, f0 = it.f0, h = d.h, M = d.M, lbufp = d.lbufp;
     const T *grid = (const T *)a.in;
+    int buf_off = 0;
+    if (TWL) {
+        for (int k = threadIdx.x; k < d.L; k += kFftThreads) buf[k] = W[k];
+        buf_off = d.L;
+        buf += d.L;
+    }
 
     // 1. z_k = g_{2k} + i g_{2k+1}; Bluestein: times the chirp, zero-padded to L
     const int span = d.blue ? d.L : h;
@@ -350,7 +371,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_r2c(FftArgs a)
         buf[f * lbufp + pad(k)] = z;
     }
     __syncthreads();
-    dft_h<T, CAP>(buf, d, nf, W, bhat);
+    dft_h<T, CAP, TWL>(buf_off, d, nf, W, bhat);
     // 3. split: Y_m = (Z_m + conj Z_{h-m}) / 2 - (i/2) e^{-2 pi i m / n} (Z_m - conj Z_{h-m})
     const T scale = a.adjoint ? T(1) : T(1.0 / d.n);
     C2<T> *four = (C2<T> *)a.out + d.four_off;
@@ -382,7 +403,7 @@ bool check_fft(const Plan &p, int cap)
     for (const RingDesc &d : p.rings) {
         if (d.lbuf > cap || d.L > d.lbuf || d.h + 1 > d.lbuf || d.M >= d.h) SHTX_FFT_FAIL;
         if (d.lbufp < d.lbuf + (d.lbuf - 1) / 8 + 1) SHTX_FFT_FAIL;  // pad(lbuf - 1) < lbufp
-        if ((size_t)d.fb * d.lbufp * celem > (size_t)p.fft_lds_bytes) SHTX_FFT_FAIL;
+        if ((size_t)(d.fb * d.lbufp + (p.fft_tw_lds ? d.L : 0)) * celem > (size_t)p.fft_lds_bytes) SHTX_FFT_FAIL;
         if (d.tw_off < 0 || d.tw_off + d.L > p.twid_elems) SHTX_FFT_FAIL;
         if (d.post_off < 0 || d.post_off + d.h + 1 > p.twid_elems) SHTX_FFT_FAIL;
         if (d.blue && (d.chirp_off < 0 || d.chirp_off + d.h > p.twid_elems || d.bhat_off < 0 ||
@@ -417,11 +438,13 @@ hipError_t launch_fft(const Plan &p, const void *in, void *out, bool adjoint, hi
         return hipErrorInvalidValue;
     }
     FftArgs a{p.d_rings, p.d_fft_items, p.d_twid, in, out, p.nfld, adjoint ? 1 : 0, p.npts};
-    auto kern = C2R ? k_fft_c2r<T, CAP> : k_fft_r2c<T, CAP>;
+    auto kern = C2R ? (p.fft_tw_lds ? k_fft_c2r<T, CAP, true> : k_fft_c2r<T, CAP, false>)
+                    : (p.fft_tw_lds ? k_fft_r2c<T, CAP, true> : k_fft_r2c<T, CAP, false>);
     // raise the kernel's dynamic-LDS limit when a plan needs more than any
     // earlier one (above 64 KiB it must be requested explicitly)
-    static int attr_bytes = 0;
-    if (p.fft_lds_bytes > attr_bytes) {
+    static int attr_bytes[2] = {0, 0};
+    int &ab = attr_bytes[p.fft_tw_lds ? 1 : 0];
+    if (p.fft_lds_bytes > ab) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, p.fft_lds_bytes);
         if (e != hipSuccess) {
@@ -429,7 +452,7 @@ hipError_t launch_fft(const Plan &p, const void *in, void *out, bool adjoint, hi
                 std::fprintf(stderr, "shtx: dynamic LDS limit %d bytes refused\n", p.fft_lds_bytes);
             return e;
         }
-        attr_bytes = p.fft_lds_bytes;
+        ab = p.fft_lds_bytes;
     }
     kern<<<(int)p.fft_items.size(), kFftThreads, p.fft_lds_bytes, s>>>(a);
     return hipGetLastError();

@@ -97,7 +97,7 @@ struct __attribute__((aligned(2 * sizeof(T)))) Vec2 {
 };
 
 template <typename T, int BM, int BN, int BK, bool INV>
-__global__ __launch_bounds__(256) void k_leg_mfma(GemmArgs a)
+__global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
 {
     constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
     constexpr int LDA = BM + 16, LDB = BN + 16;

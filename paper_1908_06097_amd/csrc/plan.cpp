@@ -336,6 +336,11 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
     }
     p.npts = goff;
     p.nfour = foff / F;
+    // twiddle tables go to LDS when every block still fits in 160 KiB with them
+    int lds_tw = 0;
+    for (const RingDesc &d : p.rings) lds_tw = std::max(lds_tw, d.fb * d.lbufp + d.L);
+    p.fft_tw_lds = (size_t)lds_tw * celem <= 160 * 1024;
+    if (p.fft_tw_lds) lds_elems = lds_tw;
     p.fft_lds_bytes = lds_elems * (int)celem;
     p.fft_lds_max = lds_elems;
     if (p.fft_lds_bytes > 160 * 1024) return SHTX_EUNSUPPORTED;

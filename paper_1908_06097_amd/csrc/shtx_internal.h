@@ -83,6 +83,7 @@ struct Plan {
     std::vector<FftItem> fft_items;
     int fft_lds_bytes = 0;
     int fft_lds_max = 0;  // complex entries of LDS the largest FFT block may use
+    bool fft_tw_lds = false;  // FFT blocks stage their twiddle table in LDS
 
     // Device memory.
     double *d_mu = nullptr, *d_w = nullptr;  // nlat
