@@ -78,9 +78,10 @@ struct FftArgs {
     int64_t npts;
 };
 
-// Forward radix-R DFT of v in registers; wr[t] = exp(-2 pi i t / R).
-template <typename T, int R>
-__device__ inline void dft_reg(C2<T> *v, const C2<T> *wr)
+// Forward radix-R DFT of v in registers; wr(t) = exp(-2 pi i t / R) is read
+// through an accessor (a register table or the twiddle table in memory).
+template <typename T, int R, typename WR>
+__device__ inline void dft_reg(C2<T> *v, WR wr)
 {
     if constexpr (R == 2) {
         C2<T> a = v[0], b = v[1];
@@ -128,7 +129,7 @@ __device__ inline void dft_reg(C2<T> *v, const C2<T> *wr)
             C2<T> re = x0, im = {T(0), T(0)};
 #pragma unroll
             for (int r = 1; r <= H; ++r) {
-                C2<T> w = wr[(k * r) % R];  // (cos, -sin) of 2 pi k r / R
+                C2<T> w = wr((k * r) % R);  // (cos, -sin) of 2 pi k r / R
                 re.x += sum[r - 1].x * w.x;
                 re.y += sum[r - 1].y * w.x;
                 im.x += dif[r - 1].x * w.y;
@@ -154,12 +155,13 @@ __device__ inline int pad(int i) { return i + (i >> 3); }
 // One in-place Stockham pass of radix R over nf fields of length L in LDS:
 // every thread reads all of its butterflies into registers, the block
 // synchronises, then each butterfly is twiddled, transformed and written.
-template <typename T, int R, int CAP, bool TWL>
-__device__ __attribute__((noinline)) void stockham_pass(int buf_off, int lbufp, int nf, int L, int Ns,
-                                                        const C2<T> *Wg)
+template <typename T>
+using GlobalC2 = const __attribute__((address_space(1))) C2<T>;
+
+template <typename T, int R, int CAP, bool TWL, typename WPtr>
+__device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lbufp, int nf, int L, int Ns, WPtr W)
 {
     C2<T> *buf = reinterpret_cast<C2<T> *>(fft_smem) + buf_off;
-    const C2<T> *W = TWL ? reinterpret_cast<const C2<T> *>(fft_smem) : Wg;
     constexpr int NB = (CAP / R + kFftThreads - 1) / kFftThreads;
     const int nbf = L / R, total = nf * nbf;
     const int tstep = L / (Ns * R);
@@ -176,11 +178,20 @@ __device__ __attribute__((noinline)) void stockham_pass(int buf_off, int lbufp, 
         }
     }
     __syncthreads();
-    C2<T> wr[R];
-    if constexpr (R != 2 && R != 4 && R != 8) {
+    // R-th roots of unity: W[t * L / R]; radix 3 and 5 keep them in
+    // registers, larger odd radices read them from the table when needed
+    C2<T> wreg[R <= 5 ? R : 1];
+    if constexpr (R == 3 || R == 5) {
 #pragma unroll
-        for (int t = 0; t < R; ++t) wr[t] = W[t * (L / R)];
+        for (int t = 0; t < R; ++t) wreg[t] = C2<T>{W[t * (L / R)].x, W[t * (L / R)].y};
     }
+    const int rstep = L / R;
+    auto wr = [&](int t) -> C2<T> {
+        if constexpr (R <= 5)
+            return wreg[t];
+        else
+            return C2<T>{W[t * rstep].x, W[t * rstep].y};
+    };
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         int e = threadIdx.x + b * kFftThreads;
@@ -191,7 +202,7 @@ __device__ __attribute__((noinline)) void stockham_pass(int buf_off, int lbufp, 
                 if constexpr (R <= 8) {
                     // twiddles w^r, w = exp(-2 pi i k / (Ns R)), from one table
                     // load and products of w, w^2, w^4 (at most three deep)
-                    C2<T> w1 = W[k * tstep];
+                    C2<T> w1 = {W[k * tstep].x, W[k * tstep].y};
                     C2<T> w2 = cmul(w1, w1);
                     C2<T> w4 = cmul(w2, w2);
 #pragma unroll
@@ -203,7 +214,7 @@ __device__ __attribute__((noinline)) void stockham_pass(int buf_off, int lbufp, 
                     }
                 } else {
 #pragma unroll
-                    for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], W[k * r * tstep]);
+                    for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], C2<T>{W[k * r * tstep].x, W[k * r * tstep].y});
                 }
             }
             dft_reg<T, R>(v[b], wr);
@@ -214,6 +225,18 @@ __device__ __attribute__((noinline)) void stockham_pass(int buf_off, int lbufp, 
         }
     }
     __syncthreads();
+}
+
+// Twiddles from LDS (TWL) or from the global table, each through a typed
+// pointer so that the pass uses ds_* or global_* instructions.
+template <typename T, int R, int CAP, bool TWL>
+__device__ inline void stockham_pass(int buf_off, int lbufp, int nf, int L, int Ns, const C2<T> *Wg)
+{
+    if constexpr (TWL)
+        stockham_pass_impl<T, R, CAP, TWL>(buf_off, lbufp, nf, L, Ns,
+                                           reinterpret_cast<const C2<T> *>(fft_smem));
+    else
+        stockham_pass_impl<T, R, CAP, TWL>(buf_off, lbufp, nf, L, Ns, (GlobalC2<T> *)Wg);
 }
 
 template <typename T, int CAP, bool TWL>
@@ -228,8 +251,6 @@ __device__ void fft_forward(int buf_off, const RingDesc &d, int nf, const C2<T> 
         case 4: stockham_pass<T, 4, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
         case 5: stockham_pass<T, 5, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
         case 7: stockham_pass<T, 7, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
-        case 11: stockham_pass<T, 11, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
-        case 13: stockham_pass<T, 13, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
         default: stockham_pass<T, 8, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
         }
         Ns *= R;
@@ -265,7 +286,7 @@ __device__ inline C2<T> dft_out(const C2<T> *slot, const RingDesc &d, const C2<T
 }
 
 template <typename T, int CAP, bool TWL>
-__global__ __launch_bounds__(kFftThreads) void k_fft_c2r(FftArgs a)
+__global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
 {
     C2<T> *buf = reinterpret_cast<C2<T> *>(fft_smem);
     const int item = xcd_remap(blockIdx.x, gridDim.x);
@@ -338,7 +359,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_c2r(FftArgs a)
 }
 
 template <typename T, int CAP, bool TWL>
-__global__ __launch_bounds__(kFftThreads) void k_fft_r2c(FftArgs a)
+__global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
 {
     C2<T> *buf = reinterpret_cast<C2<T> *>(fft_smem);
     const int item = xcd_remap(blockIdx.x, gridDim.x);
@@ -415,7 +436,7 @@ bool check_fft(const Plan &p, int cap)
         for (int s = 0; s < d.nrad; ++s) {
             int R = (int)((d.radcode >> (5 * s)) & 31u);
             bool ok = R == 4 || R == 8;
-            for (int q : {2, 3, 5, 7, 11, 13}) ok = ok || R == q;
+            for (int q : {2, 3, 5, 7}) ok = ok || R == q;
             if (!ok) SHTX_FFT_FAIL;
             prod *= R;
         }

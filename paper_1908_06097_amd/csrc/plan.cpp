@@ -28,7 +28,7 @@ int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 // Radices the ring-FFT kernel implements directly (primes; 4 and 8 are
 // formed from the factors of 2).
-const int kPrimeRadices[] = {2, 3, 5, 7, 11, 13};
+const int kPrimeRadices[] = {2, 3, 5, 7};
 
 // Factor n over the direct prime radices; returns the unfactored remainder.
 int smooth_factor(int n, std::vector<int> &f)
@@ -339,7 +339,8 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
     // twiddle tables go to LDS when every block still fits in 160 KiB with them
     int lds_tw = 0;
     for (const RingDesc &d : p.rings) lds_tw = std::max(lds_tw, d.fb * d.lbufp + d.L);
-    p.fft_tw_lds = (size_t)lds_tw * celem <= 160 * 1024;
+    // (only while two blocks still fit one CU's 160 KiB)
+    p.fft_tw_lds = (size_t)lds_tw * celem <= 80 * 1024;
     if (p.fft_tw_lds) lds_elems = lds_tw;
     p.fft_lds_bytes = lds_elems * (int)celem;
     p.fft_lds_max = lds_elems;

@@ -17,9 +17,9 @@ namespace shtx {
 constexpr int kTablePad = 128;
 
 // Ring-FFT kernels hold at most this many complex values of one block in LDS.
-constexpr int kFftCapF32 = 8192;  // 64 KiB
+constexpr int kFftCapF32 = 6144;  // 48 KiB before padding
 constexpr int kFftCapF64 = 6144;  // 96 KiB
-constexpr int kFftThreads = 1024;
+constexpr int kFftThreads = 512;
 constexpr int kMaxRadices = 12;
 
 // One m block of the Legendre tables.
