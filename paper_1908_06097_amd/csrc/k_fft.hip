@@ -87,6 +87,38 @@ __device__ inline void dft_reg(C2<T> *v, WR wr)
         C2<T> a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
+    } else if constexpr (R == 3) {
+        // X_1,2 = v0 - (v1 + v2)/2 -+ i (sqrt3/2)(v1 - v2)
+        const T r3 = T(0.86602540378443864676372317075293618347);
+        C2<T> sm = cadd(v[1], v[2]), df = csub(v[1], v[2]);
+        C2<T> t = {v[0].x - T(0.5) * sm.x, v[0].y - T(0.5) * sm.y};
+        C2<T> u = {r3 * df.y, -r3 * df.x};  // -i (sqrt3/2) df
+        v[0] = cadd(v[0], sm);
+        v[1] = cadd(t, u);
+        v[2] = csub(t, u);
+    } else if constexpr (R == 9) {
+        // 9 = 3 x 3: radix-3 over n1 for each n2 (x = v[3 n1 + n2]), twiddles
+        // exp(-2 pi i n2 k1 / 9), radix-3 over n2 for each k1
+        const C2<T> tw[5] = {{T(1), T(0)},
+                             {T(0.76604444311897803520239265055541667394), T(-0.64278760968653932632264340990726343291)},
+                             {T(0.17364817766693034885171662676931479600), T(-0.98480775301220805936674302458952301367)},
+                             {T(0), T(0)},
+                             {T(-0.93969262078590838405410927732473146993), T(-0.34202014332566873304409961468225958076)}};
+        C2<T> y[3][3];
+#pragma unroll
+        for (int n2 = 0; n2 < 3; ++n2) {
+            C2<T> t[3] = {v[n2], v[3 + n2], v[6 + n2]};
+            dft_reg<T, 3>(t, wr);
+#pragma unroll
+            for (int k1 = 0; k1 < 3; ++k1) y[n2][k1] = (n2 && k1) ? cmul(t[k1], tw[n2 * k1]) : t[k1];
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) {
+            C2<T> t[3] = {y[0][k1], y[1][k1], y[2][k1]};
+            dft_reg<T, 3>(t, wr);
+#pragma unroll
+            for (int k2 = 0; k2 < 3; ++k2) v[k1 + 3 * k2] = t[k2];
+        }
     } else if constexpr (R == 4) {
         C2<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
         C2<T> s13 = cadd(v[1], v[3]), d13 = cmi(csub(v[1], v[3]));
@@ -111,6 +143,29 @@ __device__ inline void dft_reg(C2<T> *v, WR wr)
         v[6] = csub(e[2], o2);
         v[3] = cadd(e[3], o3);
         v[7] = csub(e[3], o3);
+    } else if constexpr (R == 16) {
+        // 16 = 4 x 4: radix-4 DFTs over n1 for each n2 (x = v[4 n1 + n2]),
+        // twiddles exp(-2 pi i n2 k1 / 16), radix-4 DFTs over n2 for each k1
+        const T c1 = T(0.92387953251128675612818318939678828682);  // cos(pi/8)
+        const T s1 = T(0.38268343236508977172845998403039886676);  // sin(pi/8)
+        const T h = T(0.70710678118654752440084436210484903928);
+        const C2<T> tw[10] = {{T(1), T(0)}, {c1, -s1}, {h, -h}, {s1, -c1}, {T(0), T(-1)},
+                              {-s1, -c1}, {-h, -h}, {-c1, -s1}, {T(-1), T(0)}, {-c1, s1}};
+        C2<T> y[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            C2<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+            dft_reg<T, 4>(t, wr);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = (n2 && k1) ? cmul(t[k1], tw[n2 * k1]) : t[k1];
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            C2<T> t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+            dft_reg<T, 4>(t, wr);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+        }
     } else {
         // odd R: pair r with R - r
         constexpr int H = (R - 1) / 2;
@@ -178,16 +233,16 @@ __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lb
         }
     }
     __syncthreads();
-    // R-th roots of unity: W[t * L / R]; radix 3 and 5 keep them in
-    // registers, larger odd radices read them from the table when needed
-    C2<T> wreg[R <= 5 ? R : 1];
-    if constexpr (R == 3 || R == 5) {
+    // R-th roots of unity W[t * L / R] for the generic odd butterflies: radix 5
+    // keeps them in registers, radix 7 reads them from the table when needed
+    C2<T> wreg[R == 5 ? R : 1];
+    if constexpr (R == 5) {
 #pragma unroll
         for (int t = 0; t < R; ++t) wreg[t] = C2<T>{W[t * (L / R)].x, W[t * (L / R)].y};
     }
     const int rstep = L / R;
     auto wr = [&](int t) -> C2<T> {
-        if constexpr (R <= 5)
+        if constexpr (R == 5)
             return wreg[t];
         else
             return C2<T>{W[t * rstep].x, W[t * rstep].y};
@@ -251,6 +306,8 @@ __device__ void fft_forward(int buf_off, const RingDesc &d, int nf, const C2<T> 
         case 4: stockham_pass<T, 4, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
         case 5: stockham_pass<T, 5, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
         case 7: stockham_pass<T, 7, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
+        case 9: stockham_pass<T, 9, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
+        case 16: stockham_pass<T, 16, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
         default: stockham_pass<T, 8, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
         }
         Ns *= R;
@@ -436,7 +493,7 @@ bool check_fft(const Plan &p, int cap)
         for (int s = 0; s < d.nrad; ++s) {
             int R = (int)((d.radcode >> (5 * s)) & 31u);
             bool ok = R == 4 || R == 8;
-            for (int q : {2, 3, 5, 7}) ok = ok || R == q;
+            for (int q : {2, 3, 5, 7, 9, 16}) ok = ok || R == q;
             if (!ok) SHTX_FFT_FAIL;
             prod *= R;
         }

@@ -42,24 +42,29 @@ int smooth_factor(int n, std::vector<int> &f)
     return n;
 }
 
-// Stockham radices for a smooth length: the odd primes first, largest first
-// (the first pass needs no twiddles, so the costliest butterflies go there),
-// then as many radix-8 passes as the power of two allows, then a 4 or 2.
+// Stockham radices for a smooth length: the odd factors first, largest
+// first (the first pass needs no twiddles), with pairs of 3 merged into 9;
+// then the power of two as radix-16 passes and one 8, 4 or 2.
 std::vector<int> radices_for(int L)
 {
     std::vector<int> f;
     smooth_factor(L, f);
-    int twos = 0;
+    int twos = 0, threes = 0;
     std::vector<int> odd;
     for (int p : f) {
         if (p == 2)
             ++twos;
+        else if (p == 3)
+            ++threes;
         else
             odd.push_back(p);
     }
+    for (; threes >= 2; threes -= 2) odd.push_back(9);
+    if (threes) odd.push_back(3);
     std::sort(odd.rbegin(), odd.rend());
     std::vector<int> r(odd.begin(), odd.end());
-    for (; twos >= 3; twos -= 3) r.push_back(8);
+    for (; twos >= 4; twos -= 4) r.push_back(16);
+    if (twos == 3) r.push_back(8);
     if (twos == 2) r.push_back(4);
     if (twos == 1) r.push_back(2);
     return r;
