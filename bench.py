@@ -40,6 +40,9 @@ def parse():
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fields", type=int, default=1)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one 1 GiB device-to-device copy, the reference kernel that "
+                         "scales rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes")
     return ap.parse_args()
 
 
@@ -119,18 +122,22 @@ def roofline_for(res, prec):
     return out
 
 
-def traffic_for(kernel):
-    """Measured HBM bytes per launch from the committed rocprofv3 counter summary,
-    only if the kernel source is unchanged since it was taken."""
+def traffic_for(kernel, workload, prec):
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by
+    a copy kernel of known size) from the committed counter summary, only if
+    the kernel's source file is unchanged since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_1908_06097_amd", "csrc", rec["source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        if rec.get("workload") != workload or rec.get("prec") != prec:
             return None
-        return rec["kernels"].get(kernel)
+        k = rec["kernels"][kernel]
+        src = open(os.path.join(ROOT, "paper_1908_06097_amd", "csrc", k["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != k["source_sha256"]:
+            return None
+        return k["bytes_per_launch"]
     except Exception:
         return None
 
@@ -176,6 +183,12 @@ def main():
 
     wl = si.WORKLOADS[args.workload]
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print(f"[bench] {wl.name}: generating {wl.nfld} seeded fields", file=sys.stderr, flush=True)
     spec_np = si.spectral_fields(wl.trunc, wl.key, range(wl.nfld))
     spec_host = torch.from_numpy(spec_np)
@@ -186,7 +199,7 @@ def main():
     dom = max(roof, key=lambda k: roof[k]["ms"])
     d = roof[dom]
     roofline = {"bound": d["bound"], "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"],
-                "frac": d["frac"], "traffic": traffic_for(dom), "kernel": dom}
+                "frac": d["frac"], "traffic": traffic_for(dom, wl.name, args.prec), "kernel": dom}
     line = {
         "metric": "inv+dir SH transform fields/s",
         "value": res["fields_per_s"],

@@ -1,0 +1,103 @@
+"""Summarise rocprofv3 runs of bench.py into the text files under profiles/.
+
+Usage (after the three runs listed in profiles/README.md):
+    python rocprof_summary.py <trace_dir> <fetch_dir> <write_dir> <workload> <prec> <command...>
+
+Writes profiles/<kernel>_<workload>_<prec>.md (average duration per kernel
+from the kernel trace, and HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by
+the 1 GiB calibration copy) and profiles/traffic.json (bytes per launch per
+kernel with the sha256 of the source file the kernel was built from).
+"""
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+KERNELS = {  # bench.py name -> (unused, source file the kernel is built from)
+    "legendre_inverse_gemm": ((), "k_gemm.hip"),
+    "legendre_direct_gemm": ((), "k_gemm.hip"),
+    "ring_fft_c2r": ((), "k_fft.hip"),
+    "ring_fft_r2c": ((), "k_fft.hip"),
+}
+COPY_BYTES = 1 << 30
+
+
+def classify(name):
+    if "k_leg" in name:
+        # the inverse-shaped instantiation has template argument `true`
+        inv = ("true>" in name) or ("Lb1E" in name)
+        return "legendre_inverse_gemm" if inv else "legendre_direct_gemm"
+    if "k_fft_c2r" in name:
+        return "ring_fft_c2r"
+    if "k_fft_r2c" in name:
+        return "ring_fft_r2c"
+    if "copy" in name.lower() or "elementwise" in name.lower():
+        return "copy"
+    return None
+
+
+def one(pattern):
+    files = glob.glob(pattern, recursive=True)
+    if not files:
+        raise SystemExit(f"no file matches {pattern}")
+    return files[0]
+
+
+def main():
+    trace, fetch, write, workload, prec = sys.argv[1:6]
+    command = " ".join(sys.argv[6:])
+    stats = list(csv.DictReader(open(one(os.path.join(trace, "**", "*kernel_stats.csv")))))
+    dur = {}
+    for r in stats:
+        k = classify(r["Name"])
+        if k and k != "copy":
+            dur[k] = (float(r["AverageNs"]) / 1e6, int(r["Calls"]), r["Name"])
+
+    def counter(d, cname):
+        rows = list(csv.DictReader(open(one(os.path.join(d, "**", "*counter_collection.csv")))))
+        per = {}
+        for r in rows:
+            if r["Counter_Name"] != cname:
+                continue
+            k = classify(r["Kernel_Name"])
+            if k == "copy" and float(r["Counter_Value"]) * 1024 < COPY_BYTES / 2:
+                continue  # the fill kernels of the calibration tensors, not the copy
+            if k:
+                per.setdefault(k, []).append(float(r["Counter_Value"]))
+        return per
+
+    fr, wr = counter(fetch, "FETCH_SIZE"), counter(write, "WRITE_SIZE")
+    f_scale = COPY_BYTES / (max(fr["copy"]) * 1024)
+    w_scale = COPY_BYTES / (max(wr["copy"]) * 1024)
+    out = {"workload": workload, "prec": prec, "command": command,
+           "copy_calibration": {"fetch_scale": f_scale, "write_scale": w_scale}, "kernels": {}}
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    for k, (_, src) in KERNELS.items():
+        if k not in dur:
+            continue
+        fb = statistics.mean(fr.get(k, [0])) * 1024 * f_scale
+        wb = statistics.mean(wr.get(k, [0])) * 1024 * w_scale
+        sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1908_06097_amd", "csrc", src), "rb").read()).hexdigest()
+        out["kernels"][k] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                             "avg_ms": dur[k][0], "calls": dur[k][1], "source": src, "source_sha256": sha}
+        tag = workload.lower().replace(" ", "_")
+        with open(os.path.join(ROOT, "profiles", f"{k}_{tag}_{prec}.md"), "w") as fh:
+            fh.write(f"# {k} — {workload}, {prec}\n\n")
+            fh.write(f"Kernel: `{dur[k][2]}`\n\n")
+            fh.write(f"* rocprofv3 kernel trace: {dur[k][1]} launches, average {dur[k][0]:.3f} ms\n")
+            fh.write(f"* FETCH_SIZE per launch: {fb / 1e9:.3f} GB (raw x {f_scale:.3f}, scale from a 1 GiB copy)\n")
+            fh.write(f"* WRITE_SIZE per launch: {wb / 1e9:.3f} GB (raw x {w_scale:.3f})\n")
+            fh.write(f"* HBM traffic per launch: {(fb + wb) / 1e9:.3f} GB -> {(fb + wb) / (dur[k][0] * 1e-3) / 1e9:.0f} GB/s\n\n")
+            fh.write("Commands (run from the repository root on the GPU box):\n\n```\n")
+            fh.write(f"{command}\n```\n")
+    with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    main()
