@@ -27,7 +27,7 @@ COPY_BYTES = 1 << 30
 
 
 def classify(name):
-    if "k_leg" in name:
+    if "k_leg_mfma" in name or "k_leg_bf16x3" in name:
         # the inverse-shaped instantiation has template argument `true`
         inv = ("true>" in name) or ("Lb1E" in name)
         return "legendre_inverse_gemm" if inv else "legendre_direct_gemm"
