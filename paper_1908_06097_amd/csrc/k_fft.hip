@@ -67,9 +67,30 @@ __device__ inline C2<T> cmi(C2<T> a)
 // than through generic pointers.
 extern __shared__ __attribute__((aligned(16))) unsigned char fft_smem[];
 
+// Typed LDS pointers: address arithmetic on them stays 32-bit.
+template <typename T>
+using LdsC2 = __attribute__((address_space(3))) C2<T>;
+template <typename T>
+__device__ inline LdsC2<T> *lds_c2() { return (LdsC2<T> *)(__attribute__((address_space(3))) unsigned char *)fft_smem; }
+// One complex value in or out of LDS as a single 2-element access.
+template <typename T>
+__device__ inline C2<T> ldc(const LdsC2<T> *p)
+{
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    V2 w = *(const __attribute__((address_space(3))) V2 *)p;
+    return C2<T>{w.x, w.y};
+}
+template <typename T>
+__device__ inline void stc(LdsC2<T> *p, C2<T> v)
+{
+    typedef T V2 __attribute__((ext_vector_type(2)));
+    *(__attribute__((address_space(3))) V2 *)p = V2{v.x, v.y};
+}
+
 struct FftArgs {
     const RingDesc *rings;
     const FftItem *items;
+    const PassDesc *passes;
     const void *twid;
     const void *in;
     void *out;
@@ -78,10 +99,27 @@ struct FftArgs {
     int64_t npts;
 };
 
-// Forward radix-R DFT of v in registers; wr(t) = exp(-2 pi i t / R) is read
-// through an accessor (a register table or the twiddle table in memory).
-template <typename T, int R, typename WR>
-__device__ inline void dft_reg(C2<T> *v, WR wr)
+// exp(-2 pi i t / R) for the odd radices 5 and 7 (t taken mod R), as
+// compile-time constants.
+template <typename T, int R>
+__device__ constexpr C2<T> root(int t)
+{
+    constexpr double c5[3] = {1.0, 0.30901699437494742410229341718281905886, -0.80901699437494742410229341718281905886};
+    constexpr double s5[3] = {0.0, 0.95105651629515357211643933337938214341, 0.58778525229247312916870595463907276860};
+    constexpr double c7[4] = {1.0, 0.62348980185873353052500488400423981063, -0.22252093395631440428890256449679475947,
+                              -0.90096886790241912623610231950744505117};
+    constexpr double s7[4] = {0.0, 0.78183148246802980870844452667405775023, 0.97492791218182360701813168299393121723,
+                              0.43388373911755812047576833284835875461};
+    t %= R;
+    const int u = t <= R / 2 ? t : R - t;
+    const double c = R == 5 ? c5[u] : c7[u];
+    const double sn = R == 5 ? s5[u] : s7[u];
+    return C2<T>{T(c), T(t <= R / 2 ? -sn : sn)};
+}
+
+// Forward radix-R DFT of v in registers.
+template <typename T, int R>
+__device__ inline void dft_reg(C2<T> *v)
 {
     if constexpr (R == 2) {
         C2<T> a = v[0], b = v[1];
@@ -108,14 +146,14 @@ __device__ inline void dft_reg(C2<T> *v, WR wr)
 #pragma unroll
         for (int n2 = 0; n2 < 3; ++n2) {
             C2<T> t[3] = {v[n2], v[3 + n2], v[6 + n2]};
-            dft_reg<T, 3>(t, wr);
+            dft_reg<T, 3>(t);
 #pragma unroll
             for (int k1 = 0; k1 < 3; ++k1) y[n2][k1] = (n2 && k1) ? cmul(t[k1], tw[n2 * k1]) : t[k1];
         }
 #pragma unroll
         for (int k1 = 0; k1 < 3; ++k1) {
             C2<T> t[3] = {y[0][k1], y[1][k1], y[2][k1]};
-            dft_reg<T, 3>(t, wr);
+            dft_reg<T, 3>(t);
 #pragma unroll
             for (int k2 = 0; k2 < 3; ++k2) v[k1 + 3 * k2] = t[k2];
         }
@@ -129,8 +167,8 @@ __device__ inline void dft_reg(C2<T> *v, WR wr)
     } else if constexpr (R == 8) {
         // two radix-4 DFTs (even and odd samples) merged with exp(-2 pi i k / 8)
         C2<T> e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
-        dft_reg<T, 4>(e, wr);
-        dft_reg<T, 4>(o, wr);
+        dft_reg<T, 4>(e);
+        dft_reg<T, 4>(o);
         const T c = T(0.70710678118654752440084436210484903928);
         C2<T> o1 = {c * (o[1].x + o[1].y), c * (o[1].y - o[1].x)};   // * (1 - i)/sqrt2
         C2<T> o2 = cmi(o[2]);                                           // * -i
@@ -155,14 +193,14 @@ __device__ inline void dft_reg(C2<T> *v, WR wr)
 #pragma unroll
         for (int n2 = 0; n2 < 4; ++n2) {
             C2<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
-            dft_reg<T, 4>(t, wr);
+            dft_reg<T, 4>(t);
 #pragma unroll
             for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = (n2 && k1) ? cmul(t[k1], tw[n2 * k1]) : t[k1];
         }
 #pragma unroll
         for (int k1 = 0; k1 < 4; ++k1) {
             C2<T> t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
-            dft_reg<T, 4>(t, wr);
+            dft_reg<T, 4>(t);
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
         }
@@ -184,7 +222,7 @@ __device__ inline void dft_reg(C2<T> *v, WR wr)
             C2<T> re = x0, im = {T(0), T(0)};
 #pragma unroll
             for (int r = 1; r <= H; ++r) {
-                C2<T> w = wr((k * r) % R);  // (cos, -sin) of 2 pi k r / R
+                const C2<T> w = root<T, R>(k * r);  // (cos, -sin) of 2 pi k r / R
                 re.x += sum[r - 1].x * w.x;
                 re.y += sum[r - 1].y * w.x;
                 im.x += dif[r - 1].x * w.y;
@@ -198,85 +236,119 @@ __device__ inline void dft_reg(C2<T> *v, WR wr)
     }
 }
 
-// floor(a / b) for 0 <= a < 2^24 and b >= 1 given rb = 1/b: (a + 1/2) / b is
-// at least 1/(2b) away from an integer, far more than the rounding error of
-// the double product, so the truncation is exact (no integer division).
-__device__ inline int fdiv(int a, double rb) { return (int)(((double)a + 0.5) * rb); }
+// floor(a / d) as mul_hi(a, magic), magic = ceil(2^32 / d) (PassDesc): exact
+// for a * d < 2^32, which every caller keeps (a and d are at most a few
+// times the LDS capacity).  magic 0 stands for d = 1.
+__device__ inline int udiv(int a, unsigned magic) { return magic ? (int)__umulhi((unsigned)a, magic) : a; }
 
 // LDS slot index with one pad entry per 8 complex values: the strided writes
 // of the first Stockham passes then spread over the banks.
 __device__ inline int pad(int i) { return i + (i >> 3); }
 
+// Powers w^r (r = 1 .. R-1) of the butterfly twiddle w = exp(-2 pi i k / (Ns R))
+// from at most two table reads (w and w^3 or w^4) and products at most three
+// deep; tw[0] is unused.
+template <typename T, int R, typename WPtr>
+__device__ inline void twiddle_powers(C2<T> *tw, WPtr W, int t1)
+{
+    auto ld = [&](int t) { return C2<T>{W[t].x, W[t].y}; };
+    tw[1] = ld(t1);
+    if constexpr (R == 9) {
+        C2<T> w3 = ld(3 * t1);
+        tw[2] = cmul(tw[1], tw[1]);
+        tw[3] = w3;
+        tw[6] = cmul(w3, w3);
+#pragma unroll
+        for (int a = 3; a <= 6; a += 3)
+#pragma unroll
+            for (int b = 1; b <= 2; ++b) tw[a + b] = cmul(tw[a], tw[b]);
+    } else if constexpr (R == 16) {
+        C2<T> w4 = ld(4 * t1);
+        tw[2] = cmul(tw[1], tw[1]);
+        tw[3] = cmul(tw[1], tw[2]);
+        tw[4] = w4;
+        tw[8] = cmul(w4, w4);
+        tw[12] = cmul(w4, tw[8]);
+#pragma unroll
+        for (int a = 4; a <= 12; a += 4)
+#pragma unroll
+            for (int b = 1; b <= 3; ++b) tw[a + b] = cmul(tw[a], tw[b]);
+    } else {
+        if constexpr (R > 2) tw[2] = cmul(tw[1], tw[1]);
+        if constexpr (R > 3) tw[3] = cmul(tw[1], tw[2]);
+        if constexpr (R > 4) tw[4] = cmul(tw[2], tw[2]);
+#pragma unroll
+        for (int r = 5; r < R; ++r) tw[r] = cmul(tw[4], tw[r - 4]);
+    }
+}
+
 // One in-place Stockham pass of radix R over nf fields of length L in LDS:
 // every thread reads all of its butterflies into registers, the block
 // synchronises, then each butterfly is twiddled, transformed and written.
+// BHAT (the last pass of Bluestein's first FFT): each output X_o is replaced
+// by conj(X_o bhat_o), the pointwise step of the chirp convolution.
 template <typename T>
 using GlobalC2 = const __attribute__((address_space(1))) C2<T>;
 
-template <typename T, int R, int CAP, bool TWL, typename WPtr>
-__device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lbufp, int nf, int L, int Ns, WPtr W)
+template <typename T, int R, int CAP, bool BHAT, typename WPtr>
+__device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lbufp, int nf, PassDesc pd, WPtr W,
+                                                             GlobalC2<T> *bhat)
 {
-    C2<T> *buf = reinterpret_cast<C2<T> *>(fft_smem) + buf_off;
+    LdsC2<T> *buf = lds_c2<T>() + buf_off;
     constexpr int NB = (CAP / R + kFftThreads - 1) / kFftThreads;
-    const int nbf = L / R, total = nf * nbf;
-    const int tstep = L / (Ns * R);
-    const double rnbf = 1.0 / nbf, rNs = 1.0 / Ns;
+    const int nbf = pd.nbf, total = nf * nbf;
     C2<T> v[NB][R];
+    int fo[NB], jj[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         int e = threadIdx.x + b * kFftThreads;
         if (e < total) {
-            int f = fdiv(e, rnbf), j = e - f * nbf;
-            const C2<T> *src = buf + f * lbufp;
+            int f = udiv(e, pd.mg_nbf), j = e - f * nbf;
+            fo[b] = f * lbufp;
+            jj[b] = j;
+            const LdsC2<T> *src = buf + fo[b];
+            if (pd.nbf9) {
+                const LdsC2<T> *s0 = src + pad(j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[b][r] = src[pad(j + r * nbf)];
+                for (int r = 0; r < R; ++r) v[b][r] = ldc(s0 + r * pd.nbf9);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[b][r] = ldc(src + pad(j + r * nbf));
+            }
         }
     }
     __syncthreads();
-    // R-th roots of unity W[t * L / R] for the generic odd butterflies: radix 5
-    // keeps them in registers, radix 7 reads them from the table when needed
-    C2<T> wreg[R == 5 ? R : 1];
-    if constexpr (R == 5) {
-#pragma unroll
-        for (int t = 0; t < R; ++t) wreg[t] = C2<T>{W[t * (L / R)].x, W[t * (L / R)].y};
-    }
-    const int rstep = L / R;
-    auto wr = [&](int t) -> C2<T> {
-        if constexpr (R == 5)
-            return wreg[t];
-        else
-            return C2<T>{W[t * rstep].x, W[t * rstep].y};
-    };
+    const int Ns = pd.Ns;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         int e = threadIdx.x + b * kFftThreads;
         if (e < total) {
-            int f = fdiv(e, rnbf), j = e - f * nbf;
-            int q = fdiv(j, rNs), k = j - q * Ns;
+            int j = jj[b];
+            int q = udiv(j, pd.mg_ns), k = j - q * Ns;
             if (Ns > 1) {
-                if constexpr (R <= 8) {
-                    // twiddles w^r, w = exp(-2 pi i k / (Ns R)), from one table
-                    // load and products of w, w^2, w^4 (at most three deep)
-                    C2<T> w1 = {W[k * tstep].x, W[k * tstep].y};
-                    C2<T> w2 = cmul(w1, w1);
-                    C2<T> w4 = cmul(w2, w2);
+                C2<T> tw[R];
+                twiddle_powers<T, R>(tw, W, k * pd.tstep);
 #pragma unroll
-                    for (int r = 1; r < R; ++r) {
-                        C2<T> t = (r & 1) ? w1 : C2<T>{T(1), T(0)};
-                        if (r & 2) t = (r & 1) ? cmul(t, w2) : w2;
-                        if (r & 4) t = (r & 3) ? cmul(t, w4) : w4;
-                        v[b][r] = cmul(v[b][r], t);
-                    }
-                } else {
+                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r]);
+            }
+            dft_reg<T, R>(v[b]);
+            int base = q * Ns * R + k;
+            if constexpr (BHAT) {
 #pragma unroll
-                    for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], C2<T>{W[k * r * tstep].x, W[k * r * tstep].y});
+                for (int r = 0; r < R; ++r) {
+                    int o = base + r * Ns;
+                    v[b][r] = cconj(cmul(v[b][r], C2<T>{bhat[o].x, bhat[o].y}));
                 }
             }
-            dft_reg<T, R>(v[b], wr);
-            C2<T> *dst = buf + f * lbufp;
-            int base = q * Ns * R + k;
+            LdsC2<T> *dst = buf + fo[b];
+            if (pd.ns9) {
+                LdsC2<T> *d0 = dst + pad(base);
 #pragma unroll
-            for (int r = 0; r < R; ++r) dst[pad(base + r * Ns)] = v[b][r];
+                for (int r = 0; r < R; ++r) stc(d0 + r * pd.ns9, v[b][r]);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) stc(dst + pad(base + r * Ns), v[b][r]);
+            }
         }
     }
     __syncthreads();
@@ -284,68 +356,68 @@ __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lb
 
 // Twiddles from LDS (TWL) or from the global table, each through a typed
 // pointer so that the pass uses ds_* or global_* instructions.
-template <typename T, int R, int CAP, bool TWL>
-__device__ inline void stockham_pass(int buf_off, int lbufp, int nf, int L, int Ns, const C2<T> *Wg)
+template <typename T, int R, int CAP, bool TWL, bool BHAT>
+__device__ inline void stockham_pass(int buf_off, int lbufp, int nf, const PassDesc &pd, const C2<T> *Wg,
+                                     const C2<T> *bhat)
 {
     if constexpr (TWL)
-        stockham_pass_impl<T, R, CAP, TWL>(buf_off, lbufp, nf, L, Ns,
-                                           reinterpret_cast<const C2<T> *>(fft_smem));
+        stockham_pass_impl<T, R, CAP, BHAT>(buf_off, lbufp, nf, pd, (const LdsC2<T> *)lds_c2<T>(),
+                                            (GlobalC2<T> *)bhat);
     else
-        stockham_pass_impl<T, R, CAP, TWL>(buf_off, lbufp, nf, L, Ns, (GlobalC2<T> *)Wg);
+        stockham_pass_impl<T, R, CAP, BHAT>(buf_off, lbufp, nf, pd, (GlobalC2<T> *)Wg, (GlobalC2<T> *)bhat);
 }
 
-template <typename T, int CAP, bool TWL>
-__device__ void fft_forward(int buf_off, const RingDesc &d, int nf, const C2<T> *W)
+template <typename T, int CAP, bool TWL, bool BHAT>
+__device__ inline void pass_dispatch(int buf_off, int lbufp, int nf, const PassDesc &pd, const C2<T> *W,
+                                     const C2<T> *bhat)
 {
-    int Ns = 1;
-    for (int s = 0; s < d.nrad; ++s) {
-        int R = (int)((d.radcode >> (5 * s)) & 31u);
-        switch (R) {
-        case 2: stockham_pass<T, 2, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
-        case 3: stockham_pass<T, 3, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
-        case 4: stockham_pass<T, 4, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
-        case 5: stockham_pass<T, 5, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
-        case 7: stockham_pass<T, 7, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
-        case 9: stockham_pass<T, 9, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
-        case 16: stockham_pass<T, 16, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
-        default: stockham_pass<T, 8, CAP, TWL>(buf_off, d.lbufp, nf, d.L, Ns, W); break;
-        }
-        Ns *= R;
+    switch (pd.R) {
+    case 2: stockham_pass<T, 2, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 3: stockham_pass<T, 3, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 4: stockham_pass<T, 4, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 5: stockham_pass<T, 5, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 7: stockham_pass<T, 7, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 9: stockham_pass<T, 9, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 16: stockham_pass<T, 16, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    default: stockham_pass<T, 8, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
     }
 }
 
 // Length-h forward DFT of the h values at the start of each field slot.
 // Plain: a Stockham FFT of length h.  Bluestein: the input must already be
-// multiplied by the chirp and zero-padded to L; the result is left as
-// conj(conv) and the caller multiplies by the chirp when reading (see
-// dft_out below).
+// multiplied by the chirp and zero-padded to L; the first FFT's last pass
+// applies the filter (conj(X bhat)), the second FFT leaves conj(conv), and the
+// caller multiplies by the chirp when reading (see dft_out below).
 template <typename T, int CAP, bool TWL>
-__device__ void dft_h(int buf_off, const RingDesc &d, int nf, const C2<T> *W, const C2<T> *bhat)
+__device__ void dft_h(int buf_off, const RingDesc &d, const PassDesc *passes, int nf, const C2<T> *W,
+                      const C2<T> *bhat)
 {
-    C2<T> *buf = reinterpret_cast<C2<T> *>(fft_smem) + buf_off;
-    fft_forward<T, CAP, TWL>(buf_off, d, nf, W);
-    if (d.blue) {
-        const double rL = 1.0 / d.L;
-        for (int e = threadIdx.x; e < nf * d.L; e += kFftThreads) {
-            int f = fdiv(e, rL), k = e - f * d.L;
-            C2<T> *q = buf + f * d.lbufp + pad(k);
-            *q = cconj(cmul(*q, bhat[k]));
-        }
-        __syncthreads();
-        fft_forward<T, CAP, TWL>(buf_off, d, nf, W);
+    const PassDesc *ps = passes + d.pass_off;
+    for (int s = 0; s < d.nrad; ++s) {
+        const PassDesc pd = ps[s];
+        if (d.blue && s == d.nrad - 1)
+            pass_dispatch<T, CAP, TWL, true>(buf_off, d.lbufp, nf, pd, W, bhat);
+        else
+            pass_dispatch<T, CAP, TWL, false>(buf_off, d.lbufp, nf, pd, W, bhat);
     }
+    if (d.blue)
+        for (int s = 0; s < d.nrad; ++s) {
+            const PassDesc pd = ps[s];
+            pass_dispatch<T, CAP, TWL, false>(buf_off, d.lbufp, nf, pd, W, bhat);
+        }
 }
 
 template <typename T>
-__device__ inline C2<T> dft_out(const C2<T> *slot, const RingDesc &d, const C2<T> *chirp, int k)
+__device__ inline C2<T> dft_out(const LdsC2<T> *slot, const RingDesc &d, const C2<T> *chirp, int k)
 {
-    return d.blue ? cmul(chirp[k], cconj(slot[pad(k)])) : slot[pad(k)];
+    const C2<T> x = ldc(slot + pad(k));
+    return d.blue ? cmul(chirp[k], cconj(x)) : x;
 }
 
 template <typename T, int CAP, bool TWL>
 __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
 {
-    C2<T> *buf = reinterpret_cast<C2<T> *>(fft_smem);
+    LdsC2<T> *buf = lds_c2<T>();
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const FftItem it = a.items[item];
     if (it.ring < 0) return;
@@ -357,19 +429,20 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
     const int nf = it.nf, f0 = it.f0, h = d.h, M = d.M, lbufp = d.lbufp;
     const C2<T> *four = (const C2<T> *)a.in + d.four_off;
     const T facpos = a.adjoint ? T(0.5) : T(1);
-    const double rnf = 1.0 / nf;
+    const unsigned mg_nf = div_magic(nf);
     int buf_off = 0;
     if (TWL) {
         // the length-L twiddle table goes to LDS ahead of the field slots
-        for (int k = threadIdx.x; k < d.L; k += kFftThreads) buf[k] = W[k];
+        for (int k = threadIdx.x; k < d.L; k += kFftThreads) stc(buf + k, W[k]);
         buf_off = d.L;
         buf += d.L;
     }
 
-    // 1. kept coefficients Y_m (m <= M), zero up to index h (and to L for Bluestein)
-    const int span = d.blue ? d.L : h + 1;
-    for (int e = threadIdx.x; e < nf * span; e += kFftThreads) {
-        int m = fdiv(e, rnf), f = e - m * nf;
+    // 1. read the kept coefficients Y_m, Y_{h-m} (m <= M) and merge them into
+    //    the length-h sequence u = conj(Z'), Z'_m = (Y_m + conj Y_{h-m})
+    //    + i e^{2 pi i m / n} (Y_m - conj Y_{h-m}); Bluestein: times the chirp
+    //    and zero-padded to L.  Runs over fields are contiguous in memory.
+    auto coef = [&](int m, int f) -> C2<T> {
         C2<T> y = {T(0), T(0)};
         if (m <= M) {
             y = four[(int64_t)m * a.nfld + f0 + f];
@@ -378,37 +451,41 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
             else
                 y = {y.x * facpos, y.y * facpos};
         }
-        buf[f * lbufp + pad(m)] = y;
-    }
-    __syncthreads();
-    // 2. merge into the length-h sequence u = conj(Z'), Z'_m = (Y_m + conj Y_{h-m})
-    //    + i e^{2 pi i m / n} (Y_m - conj Y_{h-m}); Bluestein: times the chirp
+        return y;
+    };
+    auto zprime = [&](C2<T> a1, C2<T> a2, int mm) {
+        C2<T> A = cadd(a1, cconj(a2)), B = csub(a1, cconj(a2));
+        C2<T> t = cmul(cconj(post[mm]), B);
+        C2<T> z = {A.x - t.y, A.y + t.x};
+        C2<T> u = cconj(z);
+        return d.blue ? cmul(u, chirp[mm]) : u;
+    };
     const int hp = h / 2 + 1;
-    const double rhp = 1.0 / hp;
     for (int e = threadIdx.x; e < nf * hp; e += kFftThreads) {
-        int f = fdiv(e, rhp), m = e - f * hp;
-        C2<T> *s = buf + f * lbufp;
-        C2<T> ym = s[pad(m)], yh = s[pad(h - m)];
-        auto zprime = [&](C2<T> a1, C2<T> a2, int mm) {
-            C2<T> A = cadd(a1, cconj(a2)), B = csub(a1, cconj(a2));
-            C2<T> t = cmul(cconj(post[mm]), B);
-            C2<T> z = {A.x - t.y, A.y + t.x};
-            C2<T> u = cconj(z);
-            return d.blue ? cmul(u, chirp[mm]) : u;
-        };
+        int m = udiv(e, mg_nf), f = e - m * nf;
+        LdsC2<T> *s = buf + f * lbufp;
+        C2<T> ym = coef(m, f), yh = coef(h - m, f);
         C2<T> um = zprime(ym, yh, m);
-        if (m != 0 && m != h - m) s[pad(h - m)] = zprime(yh, ym, h - m);
-        s[pad(m)] = um;
+        if (m != 0 && m != h - m) stc(s + pad(h - m), zprime(yh, ym, h - m));
+        stc(s + pad(m), um);
+    }
+    if (d.blue) {
+        const int zl = d.L - h;
+        const unsigned mg_z = div_magic(zl);
+        for (int e = threadIdx.x; e < nf * zl; e += kFftThreads) {
+            int f = udiv(e, mg_z), k = h + e - f * zl;
+            stc(buf + f * lbufp + pad(k), C2<T>{T(0), T(0)});
+        }
     }
     __syncthreads();
-    // 3. forward DFT of length h
-    dft_h<T, CAP, TWL>(buf_off, d, nf, W, bhat);
-    // 4. z = conj(DFT(u)): even samples Re z, odd samples Im z
+    // 2. forward DFT of length h
+    dft_h<T, CAP, TWL>(buf_off, d, a.passes, nf, W, bhat);
+    // 3. z = conj(DFT(u)): even samples Re z, odd samples Im z
     const T scale = a.adjoint ? T(d.w / (2.0 * d.n)) : T(1);
     T *grid = (T *)a.out;
-    const double rh = 1.0 / h;
+    const unsigned mg_h = div_magic(h);
     for (int e = threadIdx.x; e < nf * h; e += kFftThreads) {
-        int f = fdiv(e, rh), k = e - f * h;
+        int f = udiv(e, mg_h), k = e - f * h;
         C2<T> r = dft_out(buf + f * lbufp, d, chirp, k);
         C2<T> g = {scale * r.x, -scale * r.y};
         *reinterpret_cast<C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k) = g;
@@ -418,7 +495,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
 template <typename T, int CAP, bool TWL>
 __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
 {
-    C2<T> *buf = reinterpret_cast<C2<T> *>(fft_smem);
+    LdsC2<T> *buf = lds_c2<T>();
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const FftItem it = a.items[item];
     if (it.ring < 0) return;
@@ -431,32 +508,32 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
     const T *grid = (const T *)a.in;
     int buf_off = 0;
     if (TWL) {
-        for (int k = threadIdx.x; k < d.L; k += kFftThreads) buf[k] = W[k];
+        for (int k = threadIdx.x; k < d.L; k += kFftThreads) stc(buf + k, W[k]);
         buf_off = d.L;
         buf += d.L;
     }
 
     // 1. z_k = g_{2k} + i g_{2k+1}; Bluestein: times the chirp, zero-padded to L
     const int span = d.blue ? d.L : h;
-    const double rspan = 1.0 / span;
+    const unsigned mg_span = div_magic(span);
     for (int e = threadIdx.x; e < nf * span; e += kFftThreads) {
-        int f = fdiv(e, rspan), k = e - f * span;
+        int f = udiv(e, mg_span), k = e - f * span;
         C2<T> z = {T(0), T(0)};
         if (k < h) {
             z = *reinterpret_cast<const C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k);
             if (d.blue) z = cmul(z, chirp[k]);
         }
-        buf[f * lbufp + pad(k)] = z;
+        stc(buf + f * lbufp + pad(k), z);
     }
     __syncthreads();
-    dft_h<T, CAP, TWL>(buf_off, d, nf, W, bhat);
-    // 3. split: Y_m = (Z_m + conj Z_{h-m}) / 2 - (i/2) e^{-2 pi i m / n} (Z_m - conj Z_{h-m})
+    dft_h<T, CAP, TWL>(buf_off, d, a.passes, nf, W, bhat);
+    // 2. split: Y_m = (Z_m + conj Z_{h-m}) / 2 - (i/2) e^{-2 pi i m / n} (Z_m - conj Z_{h-m})
     const T scale = a.adjoint ? T(1) : T(1.0 / d.n);
     C2<T> *four = (C2<T> *)a.out + d.four_off;
-    const double rnf = 1.0 / nf;
+    const unsigned mg_nf = div_magic(nf);
     for (int e = threadIdx.x; e < nf * (M + 1); e += kFftThreads) {
-        int m = fdiv(e, rnf), f = e - m * nf;
-        const C2<T> *s = buf + f * lbufp;
+        int m = udiv(e, mg_nf), f = e - m * nf;
+        const LdsC2<T> *s = buf + f * lbufp;
         C2<T> zm = dft_out(s, d, chirp, m);
         C2<T> zc = cconj(dft_out(s, d, chirp, m == 0 ? 0 : h - m));
         C2<T> A = cadd(zm, zc), B = csub(zm, zc);
@@ -489,12 +566,21 @@ bool check_fft(const Plan &p, int cap)
             SHTX_FFT_FAIL;
         if (d.grid_off + d.n > p.npts || d.four_off + (int64_t)(d.M + 1) * p.nfld > p.nfour * p.nfld)
             SHTX_FFT_FAIL;
+        if (d.pass_off < 0 || d.pass_off + d.nrad > (int)p.passes.size()) SHTX_FFT_FAIL;
         int prod = 1;
         for (int s = 0; s < d.nrad; ++s) {
             int R = (int)((d.radcode >> (5 * s)) & 31u);
             bool ok = R == 4 || R == 8;
             for (int q : {2, 3, 5, 7, 9, 16}) ok = ok || R == q;
             if (!ok) SHTX_FFT_FAIL;
+            // the pass descriptor must describe exactly this pass
+            const PassDesc &pd = p.passes[d.pass_off + s];
+            if (pd.R != R || pd.Ns != prod || pd.nbf * R != d.L || pd.tstep * prod * R != d.L) SHTX_FFT_FAIL;
+            if (pd.mg_nbf != div_magic(pd.nbf) || pd.mg_ns != div_magic(pd.Ns)) SHTX_FFT_FAIL;
+            if (pd.nbf9 != (pd.nbf % 8 ? 0 : pd.nbf / 8 * 9) || pd.ns9 != (pd.Ns % 8 ? 0 : pd.Ns / 8 * 9))
+                SHTX_FFT_FAIL;
+            // twiddle reads W[c k tstep] (c = 1, and 3 or 4 for radix 9 or 16), k < Ns
+            if (prod > 1 && (int64_t)(R == 16 ? 4 : R == 9 ? 3 : 1) * (prod - 1) * pd.tstep >= d.L) SHTX_FFT_FAIL;
             prod *= R;
         }
         if (prod != d.L) SHTX_FFT_FAIL;
@@ -515,7 +601,7 @@ hipError_t launch_fft(const Plan &p, const void *in, void *out, bool adjoint, hi
         if (std::getenv("SHTX_DEBUG")) std::fprintf(stderr, "shtx: ring-FFT launch shape check failed\n");
         return hipErrorInvalidValue;
     }
-    FftArgs a{p.d_rings, p.d_fft_items, p.d_twid, in, out, p.nfld, adjoint ? 1 : 0, p.npts};
+    FftArgs a{p.d_rings, p.d_fft_items, p.d_passes, p.d_twid, in, out, p.nfld, adjoint ? 1 : 0, p.npts};
     auto kern = C2R ? (p.fft_tw_lds ? k_fft_c2r<T, CAP, true> : k_fft_c2r<T, CAP, false>)
                     : (p.fft_tw_lds ? k_fft_r2c<T, CAP, true> : k_fft_r2c<T, CAP, false>);
     // raise the kernel's dynamic-LDS limit when a plan needs more than any

@@ -149,7 +149,7 @@ void free_plan(Plan &p)
 {
     void *ptrs[] = {p.d_mu, p.d_w, p.d_diag, p.d_tab_kr, p.d_tab_rk, p.d_tab_kr_lo,
                     p.d_tab_rk_lo, p.d_mmax, p.d_mb, p.d_inv_items, p.d_dir_items,
-                    p.d_rings, p.d_ring_four_off, p.d_fft_items, p.d_twid, p.d_four};
+                    p.d_rings, p.d_ring_four_off, p.d_fft_items, p.d_passes, p.d_twid, p.d_four};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &g : p.graphs)
@@ -238,7 +238,7 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
     const bool dbl = prec == SHTX_FP64;
     const int cap = dbl ? kFftCapF64 : kFftCapF32;
     struct LenPlan {
-        int L, blue;
+        int L, blue, pass_off;
         std::vector<int> rad;
         int64_t tw, post, chirp, bhat;
     };
@@ -270,6 +270,19 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         if (std::max(lp.L, h + 1) > cap) return SHTX_EUNSUPPORTED;
         lp.rad = radices_for(lp.L);
         if ((int)lp.rad.size() > kMaxRadices) return SHTX_EUNSUPPORTED;
+        lp.pass_off = (int)p.passes.size();
+        for (int s = 0, Ns = 1; s < (int)lp.rad.size(); Ns *= lp.rad[s], ++s) {
+            PassDesc q{};
+            q.R = lp.rad[s];
+            q.Ns = Ns;
+            q.nbf = lp.L / q.R;
+            q.tstep = lp.L / (Ns * q.R);
+            q.mg_nbf = div_magic(q.nbf);
+            q.mg_ns = div_magic(Ns);
+            q.nbf9 = q.nbf % 8 == 0 ? q.nbf / 8 * 9 : 0;
+            q.ns9 = Ns % 8 == 0 ? Ns / 8 * 9 : 0;
+            p.passes.push_back(q);
+        }
         auto push = [&](long double re, long double im) {
             pool.push_back(re);
             pool.push_back(im);
@@ -318,6 +331,7 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         d.L = lp.L;
         d.blue = lp.blue;
         d.nrad = (int)lp.rad.size();
+        d.pass_off = lp.pass_off;
         d.radcode = 0;
         for (int r = 0; r < d.nrad; ++r) d.radcode |= (unsigned long long)lp.rad[r] << (5 * r);
         d.lbuf = std::max(d.L, d.h + 1);
@@ -449,6 +463,7 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
         PLAN_TRY(upload(&p.d_ring_four_off, fo));
     }
     PLAN_TRY(upload(&p.d_fft_items, p.fft_items));
+    PLAN_TRY(upload(&p.d_passes, p.passes));
     PLAN_TRY(upload(&p.d_inv_items, p.inv_items));
     PLAN_TRY(upload(&p.d_dir_items, p.dir_items));
 

@@ -50,6 +50,7 @@ struct RingDesc {
     int fb;       // fields per FFT block for this ring
     int lbuf;     // complex values per field slot: max(L, h + 1)
     int lbufp;    // LDS entries per field slot with one pad per 8 values
+    int pass_off; // first PassDesc of this ring length's Stockham passes
     unsigned long long radcode;  // radix of pass s in bits [5s, 5s + 5)
     int64_t tw_off;     // W_L[k] = exp(-2 pi i k / L), k < L
     int64_t post_off;   // exp(-2 pi i m / n), m <= h
@@ -59,6 +60,21 @@ struct RingDesc {
     int64_t four_off;   // first complex of the ring's [m][nfld] block
     double w;           // Gauss weight
 };
+
+// One Stockham pass of a ring length's FFT (shared by every ring of that
+// length).  Divisions by nbf and Ns are done as mul_hi(a, magic) with
+// magic = ceil(2^32 / d), exact for a * d < 2^32 (magic 0 stands for d = 1).
+struct PassDesc {
+    int R;          // radix
+    int Ns;         // product of the radices of the earlier passes
+    int nbf;        // butterflies per field: L / R
+    int tstep;      // twiddle table stride of the butterfly index: L / (Ns R)
+    unsigned mg_nbf, mg_ns;
+    int nbf9;       // padded read stride nbf * 9 / 8 when 8 | nbf, else 0
+    int ns9;        // padded write stride Ns * 9 / 8 when 8 | Ns, else 0
+};
+
+__host__ __device__ inline unsigned div_magic(int d) { return d <= 1 ? 0u : 0xFFFFFFFFu / (unsigned)d + 1u; }
 
 // One FFT work item: a ring and a run of fields (ring < 0: no work).
 struct FftItem {
@@ -81,6 +97,7 @@ struct Plan {
     int inv_bm = 0, inv_bn = 0, dir_bm = 0, dir_bn = 0;
     std::vector<GemmItem> inv_items, dir_items;
     std::vector<FftItem> fft_items;
+    std::vector<PassDesc> passes;
     int fft_lds_bytes = 0;
     int fft_lds_max = 0;  // complex entries of LDS the largest FFT block may use
     bool fft_tw_lds = false;  // FFT blocks stage their twiddle table in LDS
@@ -96,6 +113,7 @@ struct Plan {
     RingDesc *d_rings = nullptr;
     int64_t *d_ring_four_off = nullptr;  // per ring: RingDesc::four_off
     FftItem *d_fft_items = nullptr;
+    PassDesc *d_passes = nullptr;
     void *d_twid = nullptr;  // FFT twiddle pool (complex, grid precision)
     int64_t twid_elems = 0;  // complex entries in the pool
     std::vector<double> twid_host;  // pool (re, im) before upload
