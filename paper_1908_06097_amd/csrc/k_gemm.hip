@@ -68,8 +68,8 @@ struct GemmArgs {
     const void *tab_lo;  // split-BF16 lo half of the table
     const MBlock *mb;
     const GemmItem *items;
-    const int64_t *four_off;  // per ring: first complex of its [m][nfld] block
-    const double *wq;         // per ring: Gauss weight
+    const RingPair *ring_pair;  // per northern ring: Fourier offsets of it and its mirror
+    const void *ring_q;         // per northern ring: w_j / 2 (grid precision)
     const void *in;
     void *out;
     int trunc, nlat, nfld;
@@ -106,8 +106,10 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
     // complex operand loads per thread per stage: INV reads BN/2 fields x 2 BK
     // coefficients, DIR reads BK rings x BN/2 fields (north and south each)
     constexpr int NB = INV ? (BK * BN) / 256 : (BK * BN) / 512;
+    constexpr int NM = INV ? 1 : NB;  // ring metadata per thread (DIR)
     static_assert(NA * VEC * 256 == 2 * BK * BM, "table tile must split evenly");
     static_assert(NB * (INV ? 256 : 512) == BK * BN, "operand tile must split evenly");
+    static_assert(BK == 16 && BN >= 32, "operand swizzle assumes 16-deep stages");
     typedef typename Acc<T>::type V;
     typedef T VecT __attribute__((ext_vector_type(VEC)));
     __shared__ __attribute__((aligned(16))) T As[2][2][BK][LDA];
@@ -129,9 +131,34 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
     const int kend = INV ? b.K0 : b.R;
     const int nstages = (kend + BK - 1) / BK;
 
+    // INV stores the coefficient tile with the field index XOR-swizzled by
+    // its (parity, k) slot, so that the column-strided stores of one wave
+    // hit distinct LDS banks; the MFMA reads undo the swizzle.
+    auto bswz = [](int p, int q) { return 2 * (((q >> 1) & 3) | (p << 2)); };
+
     VecT ra[NA];
     Vec2<T> rb0[NB], rb1[NB];
+    // DIR: Fourier offsets and weights of each thread's rings, fetched one
+    // stage ahead of the data so that no data load waits on them
+    RingPair mp1[NM], mp2[NM];
+    T mq1[NM], mq2[NM];
 
+    auto meta = [&](int kk, RingPair *mp, T *mq) {
+#pragma unroll
+        for (int v = 0; v < NM; ++v) {
+            int r = kk + (tid + v * 256) / (BN / 2);
+            RingPair o = {-1, -1};
+            T w = T(0);
+            if (r < b.R) {
+                o = a.ring_pair[b.j0 + r];
+                w = a.adjoint ? T(1) : ((const T *)a.ring_q)[b.j0 + r];
+            }
+            mp[v] = o;
+            mq[v] = w;
+        }
+    };
+    // global -> registers (no arithmetic on the loaded values here, so that
+    // nothing waits for the loads before the MFMAs of the current stage)
     auto load = [&](int kk) {
 #pragma unroll
         for (int v = 0; v < NA; ++v) {
@@ -148,10 +175,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
                 int fl = idx / (2 * BK), t = idx - fl * (2 * BK);
                 int f = col0 / 2 + fl, nrel = 2 * kk + t;
                 Vec2<T> z = {T(0), T(0)};
-                if (f < a.nfld && m + nrel <= a.trunc) {
-                    z = spec[(int64_t)f * a.nspec + sb + nrel];
-                    if (m == 0) z.y = T(0);
-                }
+                if (f < a.nfld && m + nrel <= a.trunc) z = spec[(int64_t)f * a.nspec + sb + nrel];
                 rb0[v] = z;
             }
         } else {
@@ -159,22 +183,19 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
 #pragma unroll
             for (int v = 0; v < NB; ++v) {
                 int idx = tid + v * 256;
-                int q = idx / (BN / 2), cp = idx - q * (BN / 2);
-                int r = kk + q, f = col0 / 2 + cp;
-                Vec2<T> s0 = {T(0), T(0)}, s1 = {T(0), T(0)};
-                if (r < b.R && f < a.nfld) {
-                    int jn = b.j0 + r, js = a.nlat - 1 - jn;
-                    Vec2<T> gn = four[a.four_off[jn] + (int64_t)m * a.nfld + f];
-                    Vec2<T> gs = four[a.four_off[js] + (int64_t)m * a.nfld + f];
-                    T q_r = a.adjoint ? T(1) : T(0.5 * a.wq[jn]);
-                    s0 = {q_r * (gn.x + gs.x), q_r * (gn.y + gs.y)};
-                    s1 = {q_r * (gn.x - gs.x), q_r * (gn.y - gs.y)};
+                int cp = idx % (BN / 2);
+                int f = col0 / 2 + cp;
+                Vec2<T> gn = {T(0), T(0)}, gs = {T(0), T(0)};
+                if (mp1[v].n >= 0 && f < a.nfld) {
+                    gn = four[((int64_t)mp1[v].n + m) * a.nfld + f];
+                    gs = four[((int64_t)mp1[v].s + m) * a.nfld + f];
                 }
-                rb0[v] = s0;
-                rb1[v] = s1;
+                rb0[v] = gn;
+                rb1[v] = gs;
             }
         }
     };
+    // registers -> LDS: INV zeroes Im a^0_n, DIR folds the hemispheres
     auto store = [&](int buf) {
 #pragma unroll
         for (int v = 0; v < NA; ++v) {
@@ -189,15 +210,21 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
                 int idx = tid + v * 256;
                 int fl = idx / (2 * BK), t = idx - fl * (2 * BK);
                 int p = t & 1, q = t >> 1;
-                *reinterpret_cast<Vec2<T> *>(&Bs[buf][p][q][2 * fl]) = rb0[v];
+                Vec2<T> z = rb0[v];
+                if (m == 0) z.y = T(0);
+                *reinterpret_cast<Vec2<T> *>(&Bs[buf][p][q][(2 * fl) ^ bswz(p, q)]) = z;
             }
         } else {
 #pragma unroll
             for (int v = 0; v < NB; ++v) {
                 int idx = tid + v * 256;
                 int q = idx / (BN / 2), cp = idx - q * (BN / 2);
-                *reinterpret_cast<Vec2<T> *>(&Bs[buf][0][q][2 * cp]) = rb0[v];
-                *reinterpret_cast<Vec2<T> *>(&Bs[buf][1][q][2 * cp]) = rb1[v];
+                const T w = mq1[v];
+                const Vec2<T> gn = rb0[v], gs = rb1[v];
+                Vec2<T> s0 = {w * (gn.x + gs.x), w * (gn.y + gs.y)};
+                Vec2<T> s1 = {w * (gn.x - gs.x), w * (gn.y - gs.y)};
+                *reinterpret_cast<Vec2<T> *>(&Bs[buf][0][q][2 * cp]) = s0;
+                *reinterpret_cast<Vec2<T> *>(&Bs[buf][1][q][2 * cp]) = s1;
             }
         }
     };
@@ -210,13 +237,24 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
 #pragma unroll
             for (int j = 0; j < FN; ++j) acc[p][i][j] = V{};
 
+    // per-lane column of the B reads for each k step and parity (INV swizzle)
+    int bcol[BK / 4][2];
+#pragma unroll
+    for (int q = 0; q < BK; q += 4)
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+            bcol[q / 4][p] = INV ? ((lane & 15) ^ bswz(p, q + (lane >> 4))) : (lane & 15);
+
+    if (!INV) meta(0, mp1, mq1);
     load(0);
     store(0);
+    if (!INV && nstages > 1) meta(BK, mp1, mq1);
     __syncthreads();
     for (int s = 0; s < nstages; ++s) {
         const int cur = s & 1;
         const bool more = s + 1 < nstages;
         if (more) load((s + 1) * BK);
+        if (!INV && s + 2 < nstages) meta((s + 2) * BK, mp2, mq2);
 #pragma unroll
         for (int q = 0; q < BK; q += 4) {
             const int qq = q + (lane >> 4);
@@ -226,7 +264,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
 #pragma unroll
                 for (int i = 0; i < FM; ++i) av[i] = As[cur][p][qq][wr + i * 16 + (lane & 15)];
 #pragma unroll
-                for (int j = 0; j < FN; ++j) bv[j] = Bs[cur][p][qq][wc + j * 16 + (lane & 15)];
+                for (int j = 0; j < FN; ++j) bv[j] = Bs[cur][p][qq][wc + j * 16 + bcol[q / 4][p]];
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -234,26 +272,46 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
             }
         }
         if (more) store(cur ^ 1);
+        if (!INV && s + 2 < nstages) {
+#pragma unroll
+            for (int v = 0; v < NM; ++v) {
+                mp1[v] = mp2[v];
+                mq1[v] = mq2[v];
+            }
+        }
         __syncthreads();
     }
 
     if (INV) {
         T *four = (T *)a.out;
+        // all rows' ring offsets first, so that their loads overlap
+        RingPair ro[FM][4];
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-            for (int j = 0; j < FN; ++j)
+            for (int v = 0; v < 4; ++v) {
+                int r = row0 + wr + i * 16 + acc_row<T>(lane, v);
+                ro[i][v] = RingPair{-1, -1};
+                if (r < b.R) ro[i][v] = a.ring_pair[b.j0 + r];
+            }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    int r = row0 + wr + i * 16 + acc_row<T>(lane, v);
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const RingPair o = ro[i][v];
+                if (o.n < 0) continue;
+                T *fn = four + 2 * ((int64_t)o.n + m) * a.nfld;
+                T *fs = four + 2 * ((int64_t)o.s + m) * a.nfld;
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
                     int c = col0 + wc + j * 16 + (lane & 15);
-                    if (r < b.R && c < ncol) {
+                    if (c < ncol) {
                         T s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
-                        int jn = b.j0 + r, js = a.nlat - 1 - jn;
-                        four[2 * (a.four_off[jn] + (int64_t)m * a.nfld) + c] = s0 + s1;
-                        four[2 * (a.four_off[js] + (int64_t)m * a.nfld) + c] = s0 - s1;
+                        fn[c] = s0 + s1;
+                        fs[c] = s0 - s1;
                     }
                 }
+            }
     } else {
         T *spec = (T *)a.out;
 #pragma unroll
@@ -333,6 +391,29 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
 
     u32x4 ra[NA];
     float2 rv[NU][INVERSE ? 8 : 16];
+    // DIR: Fourier offsets and weights of each unit's 8 rings, fetched one
+    // stage ahead of the data so that no data load waits on them
+    constexpr int NMU = INVERSE ? 1 : NU, NMQ = INVERSE ? 1 : 8;
+    RingPair mp1[NMU][NMQ], mp2[NMU][NMQ];
+    float mq1[NMU][NMQ], mq2[NMU][NMQ];
+    auto meta = [&](int kk, RingPair (*mp)[NMQ], float (*mq)[NMQ]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < NMU; ++u) {
+            int rc = (tid + u * 256) / (BN / 2);
+#pragma unroll
+            for (int q = 0; q < NMQ; ++q) {
+                int r = kk + rc * 8 + q;
+                RingPair o = {-1, -1};
+                float w = 0.f;
+                if (r < b.R) {
+                    o = a.ring_pair[b.j0 + r];
+                    w = a.adjoint ? 1.f : ((const float *)a.ring_q)[b.j0 + r];
+                }
+                mp[u][q] = o;
+                mq[u][q] = w;
+            }
+        }
+    };
 
     auto load = [&](int kk) __attribute__((always_inline)) {
 #pragma unroll
@@ -357,30 +438,21 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
                 for (int q = 0; q < 8; ++q) {
                     int nrel = 2 * (kk + qc * 8 + q) + p;
                     float2 z = {0.f, 0.f};
-                    if (f < a.nfld && m + nrel <= a.trunc) {
-                        z = spec[nrel];
-                        if (m == 0) z.y = 0.f;
-                    }
+                    if (f < a.nfld && m + nrel <= a.trunc) z = spec[nrel];
                     rv[u][q] = z;
                 }
             } else {
-                // 8 consecutive rings of one field, north and south
+                // 8 consecutive rings of one field, north and south; the
+                // rings' offsets come from the previous stage's meta fetch
                 int rc = idx / (BN / 2), cp = idx - rc * (BN / 2);
                 int f = col0 / 2 + cp;
                 const float2 *four = (const float2 *)a.in;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    int r = kk + rc * 8 + q;
                     float2 gn = {0.f, 0.f}, gs = {0.f, 0.f};
-                    if (r < b.R && f < a.nfld) {
-                        int jn = b.j0 + r, js = a.nlat - 1 - jn;
-                        gn = four[a.four_off[jn] + (int64_t)m * a.nfld + f];
-                        gs = four[a.four_off[js] + (int64_t)m * a.nfld + f];
-                        float q_r = a.adjoint ? 1.f : (float)(0.5 * a.wq[jn]);
-                        gn.x *= q_r;
-                        gn.y *= q_r;
-                        gs.x *= q_r;
-                        gs.y *= q_r;
+                    if (mp1[u][q].n >= 0 && f < a.nfld) {
+                        gn = four[((int64_t)mp1[u][q].n + m) * a.nfld + f];
+                        gs = four[((int64_t)mp1[u][q].s + m) * a.nfld + f];
                     }
                     rv[u][2 * q] = gn;
                     rv[u][2 * q + 1] = gs;
@@ -423,6 +495,10 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
             if (INVERSE) {
                 int fl = idx / (2 * (BK / 8)), rem = idx - fl * 2 * (BK / 8);
                 int p = rem & 1, qc = rem >> 1;
+                if (m == 0) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) rv[u][q].y = 0.f;
+                }
 #define z rv[u]
                 split8(z[0].x, z[1].x, z[2].x, z[3].x, z[4].x, z[5].x, z[6].x, z[7].x, hi, lo);
                 *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * fl][qc * 8]) = hi;
@@ -433,6 +509,12 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
 #undef z
             } else {
                 int rc = idx / (BN / 2), cp = idx - rc * (BN / 2);
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const float w = mq1[u][q];
+                    rv[u][2 * q] = float2{w * rv[u][2 * q].x, w * rv[u][2 * q].y};
+                    rv[u][2 * q + 1] = float2{w * rv[u][2 * q + 1].x, w * rv[u][2 * q + 1].y};
+                }
 #define z rv[u]  // z[2q] north, z[2q+1] south of ring q
 #define SHTX_FOLD(c, sgn)                                                                         \
     split8(z[0].c sgn z[1].c, z[2].c sgn z[3].c, z[4].c sgn z[5].c, z[6].c sgn z[7].c,              \
@@ -463,11 +545,23 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
 #pragma unroll
             for (int j = 0; j < FN; ++j) acc[p][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+    if (!INVERSE) meta(0, mp1, mq1);
     load(0);
+    if (!INVERSE && nstages > 1) meta(BK, mp2, mq2);
     for (int s = 0; s < nstages; ++s) {
-        store();
+        store();  // uses the weights mq1 of stage s
+        if (!INVERSE && s + 1 < nstages) {
+#pragma unroll
+            for (int u = 0; u < NMU; ++u)
+#pragma unroll
+                for (int q = 0; q < NMQ; ++q) {
+                    mp1[u][q] = mp2[u][q];
+                    mq1[u][q] = mq2[u][q];
+                }
+        }
         __syncthreads();
         if (s + 1 < nstages) load((s + 1) * BK);  // in flight during the MFMAs
+        if (!INVERSE && s + 2 < nstages) meta((s + 2) * BK, mp2, mq2);
 #pragma unroll
         for (int q = 0; q < BK; q += 32) {
             const int kq = q + 8 * (lane >> 4);
@@ -504,19 +598,27 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
     const float unscale = ldexpf(1.f, -b.e);
     if (INVERSE) {
         float *four = (float *)a.out;
+        RingPair ro[FM][4];
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int r = row0 + wr + i * 16 + 4 * (lane >> 4) + v;
+                ro[i][v] = RingPair{-1, -1};
+                if (r < b.R) ro[i][v] = a.ring_pair[b.j0 + r];
+            }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    int r = row0 + wr + i * 16 + 4 * (lane >> 4) + v;
+                    const RingPair o = ro[i][v];
                     int c = col0 + wc + j * 16 + (lane & 15);
-                    if (r < b.R && c < ncol) {
+                    if (o.n >= 0 && c < ncol) {
                         float s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
-                        int jn = b.j0 + r, js = a.nlat - 1 - jn;
-                        four[2 * (a.four_off[jn] + (int64_t)m * a.nfld) + c] = (s0 + s1) * unscale;
-                        four[2 * (a.four_off[js] + (int64_t)m * a.nfld) + c] = (s0 - s1) * unscale;
+                        four[2 * ((int64_t)o.n + m) * a.nfld + c] = (s0 + s1) * unscale;
+                        four[2 * ((int64_t)o.s + m) * a.nfld + c] = (s0 - s1) * unscale;
                     }
                 }
     } else {
@@ -546,8 +648,8 @@ GemmArgs make_args(const Plan &p, bool inverse_shape, const void *in, void *out,
     GemmArgs a{};
     a.mb = p.d_mb;
     a.items = inverse_shape ? p.d_inv_items : p.d_dir_items;
-    a.four_off = p.d_ring_four_off;
-    a.wq = p.d_w;
+    a.ring_pair = p.d_ring_pair;
+    a.ring_q = p.d_ring_q;
     a.in = in;
     a.out = out;
     a.trunc = p.trunc;

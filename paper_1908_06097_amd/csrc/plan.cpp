@@ -149,7 +149,8 @@ void free_plan(Plan &p)
 {
     void *ptrs[] = {p.d_mu, p.d_w, p.d_diag, p.d_tab_kr, p.d_tab_rk, p.d_tab_kr_lo,
                     p.d_tab_rk_lo, p.d_mmax, p.d_mb, p.d_inv_items, p.d_dir_items,
-                    p.d_rings, p.d_ring_four_off, p.d_fft_items, p.d_passes, p.d_twid, p.d_four};
+                    p.d_rings, p.d_ring_four_off, p.d_ring_pair, p.d_ring_q, p.d_fft_items, p.d_passes,
+                    p.d_twid, p.d_four};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &g : p.graphs)
@@ -461,6 +462,19 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
         std::vector<int64_t> fo(nlat);
         for (int j = 0; j < nlat; ++j) fo[j] = p.rings[j].four_off;
         PLAN_TRY(upload(&p.d_ring_four_off, fo));
+        std::vector<RingPair> rp(nlat / 2);
+        for (int j = 0; j < nlat / 2; ++j)
+            rp[j] = RingPair{(int)(fo[j] / nfld), (int)(fo[nlat - 1 - j] / nfld)};
+        PLAN_TRY(upload(&p.d_ring_pair, rp));
+        if (dbl) {
+            std::vector<double> q(nlat / 2);
+            for (int j = 0; j < nlat / 2; ++j) q[j] = 0.5 * w[j];
+            PLAN_TRY(upload(reinterpret_cast<double **>(&p.d_ring_q), q));
+        } else {
+            std::vector<float> q(nlat / 2);
+            for (int j = 0; j < nlat / 2; ++j) q[j] = (float)(0.5 * w[j]);
+            PLAN_TRY(upload(reinterpret_cast<float **>(&p.d_ring_q), q));
+        }
     }
     PLAN_TRY(upload(&p.d_fft_items, p.fft_items));
     PLAN_TRY(upload(&p.d_passes, p.passes));

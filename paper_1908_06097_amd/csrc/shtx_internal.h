@@ -76,6 +76,12 @@ struct PassDesc {
 
 __host__ __device__ inline unsigned div_magic(int d) { return d <= 1 ? 0u : 0xFFFFFFFFu / (unsigned)d + 1u; }
 
+// Fourier-workspace offsets of a northern ring and its southern mirror, in
+// units of nfld complex values (RingDesc::four_off / nfld).
+struct __attribute__((aligned(8))) RingPair {
+    int n, s;
+};
+
 // One FFT work item: a ring and a run of fields (ring < 0: no work).
 struct FftItem {
     int ring, f0, nf, pad_;
@@ -112,6 +118,8 @@ struct Plan {
     GemmItem *d_inv_items = nullptr, *d_dir_items = nullptr;
     RingDesc *d_rings = nullptr;
     int64_t *d_ring_four_off = nullptr;  // per ring: RingDesc::four_off
+    RingPair *d_ring_pair = nullptr;     // per northern ring
+    void *d_ring_q = nullptr;            // per northern ring: w_j / 2 in grid precision
     FftItem *d_fft_items = nullptr;
     PassDesc *d_passes = nullptr;
     void *d_twid = nullptr;  // FFT twiddle pool (complex, grid precision)
