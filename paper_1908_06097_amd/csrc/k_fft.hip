@@ -236,6 +236,10 @@ __device__ inline void dft_reg(C2<T> *v)
     }
 }
 
+// Elements per thread whose global loads are issued together in the
+// kernels' gather and scatter loops.
+constexpr int kU = 4;
+
 // floor(a / d) as mul_hi(a, magic), magic = ceil(2^32 / d) (PassDesc): exact
 // for a * d < 2^32, which every caller keeps (a and d are at most a few
 // times the LDS capacity).  magic 0 stands for d = 1.
@@ -245,30 +249,31 @@ __device__ inline int udiv(int a, unsigned magic) { return magic ? (int)__umulhi
 // of the first Stockham passes then spread over the banks.
 __device__ inline int pad(int i) { return i + (i >> 3); }
 
-// Powers w^r (r = 1 .. R-1) of the butterfly twiddle w = exp(-2 pi i k / (Ns R))
-// from at most two table reads (w and w^3 or w^4) and products at most three
-// deep; tw[0] is unused.
-template <typename T, int R, typename WPtr>
-__device__ inline void twiddle_powers(C2<T> *tw, WPtr W, int t1)
+// The table reads behind the twiddle powers of one butterfly: w = W[t1]
+// (w = exp(-2 pi i k / (Ns R))) and, for radix 9 and 16, w^3 or w^4.
+template <int R>
+constexpr int twiddle_step2() { return R == 9 ? 3 : R == 16 ? 4 : 0; }
+
+// Powers w^r (r = 1 .. R-1) from w and the second table value, by products
+// at most three deep; tw[0] is unused.
+template <typename T, int R>
+__device__ inline void twiddle_powers(C2<T> *tw, C2<T> w1, C2<T> w2nd)
 {
-    auto ld = [&](int t) { return C2<T>{W[t].x, W[t].y}; };
-    tw[1] = ld(t1);
+    tw[1] = w1;
     if constexpr (R == 9) {
-        C2<T> w3 = ld(3 * t1);
         tw[2] = cmul(tw[1], tw[1]);
-        tw[3] = w3;
-        tw[6] = cmul(w3, w3);
+        tw[3] = w2nd;
+        tw[6] = cmul(w2nd, w2nd);
 #pragma unroll
         for (int a = 3; a <= 6; a += 3)
 #pragma unroll
             for (int b = 1; b <= 2; ++b) tw[a + b] = cmul(tw[a], tw[b]);
     } else if constexpr (R == 16) {
-        C2<T> w4 = ld(4 * t1);
         tw[2] = cmul(tw[1], tw[1]);
         tw[3] = cmul(tw[1], tw[2]);
-        tw[4] = w4;
-        tw[8] = cmul(w4, w4);
-        tw[12] = cmul(w4, tw[8]);
+        tw[4] = w2nd;
+        tw[8] = cmul(w2nd, w2nd);
+        tw[12] = cmul(w2nd, tw[8]);
 #pragma unroll
         for (int a = 4; a <= 12; a += 4)
 #pragma unroll
@@ -296,16 +301,25 @@ __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lb
 {
     LdsC2<T> *buf = lds_c2<T>() + buf_off;
     constexpr int NB = (CAP / R + kFftThreads - 1) / kFftThreads;
-    const int nbf = pd.nbf, total = nf * nbf;
+    constexpr int C2ND = twiddle_step2<R>();
+    const int nbf = pd.nbf, total = nf * nbf, Ns = pd.Ns;
     C2<T> v[NB][R];
-    int fo[NB], jj[NB];
+    C2<T> w1[NB], w2[NB];  // twiddle table values, fetched before the barrier
+    int fo[NB], qk[NB][2];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         int e = threadIdx.x + b * kFftThreads;
         if (e < total) {
             int f = udiv(e, pd.mg_nbf), j = e - f * nbf;
+            int q = udiv(j, pd.mg_ns), k = j - q * Ns;
             fo[b] = f * lbufp;
-            jj[b] = j;
+            qk[b][0] = q;
+            qk[b][1] = k;
+            if (Ns > 1) {
+                const int t1 = k * pd.tstep;
+                w1[b] = C2<T>{W[t1].x, W[t1].y};
+                if constexpr (C2ND > 0) w2[b] = C2<T>{W[C2ND * t1].x, W[C2ND * t1].y};
+            }
             const LdsC2<T> *src = buf + fo[b];
             if (pd.nbf9) {
                 const LdsC2<T> *s0 = src + pad(j);
@@ -318,25 +332,23 @@ __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lb
         }
     }
     __syncthreads();
-    const int Ns = pd.Ns;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
         int e = threadIdx.x + b * kFftThreads;
         if (e < total) {
-            int j = jj[b];
-            int q = udiv(j, pd.mg_ns), k = j - q * Ns;
+            const int q = qk[b][0], k = qk[b][1];
+            const int base = q * Ns * R + k;
             if (Ns > 1) {
                 C2<T> tw[R];
-                twiddle_powers<T, R>(tw, W, k * pd.tstep);
+                twiddle_powers<T, R>(tw, w1[b], w2[b]);
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r]);
             }
             dft_reg<T, R>(v[b]);
-            int base = q * Ns * R + k;
             if constexpr (BHAT) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    int o = base + r * Ns;
+                    const int o = base + r * Ns;
                     v[b][r] = cconj(cmul(v[b][r], C2<T>{bhat[o].x, bhat[o].y}));
                 }
             }
@@ -387,7 +399,7 @@ __device__ inline void pass_dispatch(int buf_off, int lbufp, int nf, const PassD
 // Plain: a Stockham FFT of length h.  Bluestein: the input must already be
 // multiplied by the chirp and zero-padded to L; the first FFT's last pass
 // applies the filter (conj(X bhat)), the second FFT leaves conj(conv), and the
-// caller multiplies by the chirp when reading (see dft_out below).
+// caller multiplies by the chirp when reading the first h outputs.
 template <typename T, int CAP, bool TWL>
 __device__ void dft_h(int buf_off, const RingDesc &d, const PassDesc *passes, int nf, const C2<T> *W,
                       const C2<T> *bhat)
@@ -407,12 +419,6 @@ __device__ void dft_h(int buf_off, const RingDesc &d, const PassDesc *passes, in
         }
 }
 
-template <typename T>
-__device__ inline C2<T> dft_out(const LdsC2<T> *slot, const RingDesc &d, const C2<T> *chirp, int k)
-{
-    const C2<T> x = ldc(slot + pad(k));
-    return d.blue ? cmul(chirp[k], cconj(x)) : x;
-}
 
 template <typename T, int CAP, bool TWL>
 __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
@@ -442,32 +448,54 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
     //    the length-h sequence u = conj(Z'), Z'_m = (Y_m + conj Y_{h-m})
     //    + i e^{2 pi i m / n} (Y_m - conj Y_{h-m}); Bluestein: times the chirp
     //    and zero-padded to L.  Runs over fields are contiguous in memory.
-    auto coef = [&](int m, int f) -> C2<T> {
-        C2<T> y = {T(0), T(0)};
-        if (m <= M) {
-            y = four[(int64_t)m * a.nfld + f0 + f];
-            if (m == 0)
-                y.y = T(0);
-            else
-                y = {y.x * facpos, y.y * facpos};
-        }
-        return y;
-    };
-    auto zprime = [&](C2<T> a1, C2<T> a2, int mm) {
+    //    Each thread issues the loads of kU elements before using any.
+    auto zprime = [&](C2<T> a1, C2<T> a2, C2<T> pst, C2<T> chp) {
         C2<T> A = cadd(a1, cconj(a2)), B = csub(a1, cconj(a2));
-        C2<T> t = cmul(cconj(post[mm]), B);
+        C2<T> t = cmul(cconj(pst), B);
         C2<T> z = {A.x - t.y, A.y + t.x};
         C2<T> u = cconj(z);
-        return d.blue ? cmul(u, chirp[mm]) : u;
+        return d.blue ? cmul(u, chp) : u;
     };
-    const int hp = h / 2 + 1;
-    for (int e = threadIdx.x; e < nf * hp; e += kFftThreads) {
-        int m = udiv(e, mg_nf), f = e - m * nf;
-        LdsC2<T> *s = buf + f * lbufp;
-        C2<T> ym = coef(m, f), yh = coef(h - m, f);
-        C2<T> um = zprime(ym, yh, m);
-        if (m != 0 && m != h - m) stc(s + pad(h - m), zprime(yh, ym, h - m));
-        stc(s + pad(m), um);
+    const int hp = h / 2 + 1, nmerge = nf * hp;
+    for (int e0 = threadIdx.x; e0 < nmerge; e0 += kU * kFftThreads) {
+        C2<T> ym[kU], yh[kU], pm[kU], ph[kU], cm[kU], ch[kU];
+        int mm[kU], ff[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + u * kFftThreads;
+            const bool ok = e < nmerge;
+            int m = ok ? udiv(e, mg_nf) : 0;
+            int f = ok ? e - m * nf : 0;
+            mm[u] = ok ? m : -1;
+            ff[u] = f;
+            const C2<T> zero = {T(0), T(0)};
+            ym[u] = zero;
+            yh[u] = zero;
+            if (ok && m <= M) ym[u] = four[(int64_t)m * a.nfld + f0 + f];
+            if (ok && h - m <= M) yh[u] = four[(int64_t)(h - m) * a.nfld + f0 + f];
+            pm[u] = post[m];
+            ph[u] = post[h - m];
+            cm[u] = zero;
+            ch[u] = zero;
+            if (d.blue) {
+                cm[u] = chirp[m];
+                ch[u] = chirp[m == 0 ? 0 : h - m];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int m = mm[u];
+            if (m < 0) continue;
+            C2<T> y0 = ym[u], y1 = yh[u];
+            if (m == 0)
+                y0.y = T(0);
+            else
+                y0 = {y0.x * facpos, y0.y * facpos};
+            y1 = {y1.x * facpos, y1.y * facpos};
+            LdsC2<T> *sl = buf + ff[u] * lbufp;
+            if (m != 0 && m != h - m) stc(sl + pad(h - m), zprime(y1, y0, ph[u], ch[u]));
+            stc(sl + pad(m), zprime(y0, y1, pm[u], cm[u]));
+        }
     }
     if (d.blue) {
         const int zl = d.L - h;
@@ -484,11 +512,24 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
     const T scale = a.adjoint ? T(d.w / (2.0 * d.n)) : T(1);
     T *grid = (T *)a.out;
     const unsigned mg_h = div_magic(h);
-    for (int e = threadIdx.x; e < nf * h; e += kFftThreads) {
-        int f = udiv(e, mg_h), k = e - f * h;
-        C2<T> r = dft_out(buf + f * lbufp, d, chirp, k);
-        C2<T> g = {scale * r.x, -scale * r.y};
-        *reinterpret_cast<C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k) = g;
+    for (int e0 = threadIdx.x; e0 < nf * h; e0 += kU * kFftThreads) {
+        C2<T> cp[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + u * kFftThreads;
+            const int k = e < nf * h ? e - udiv(e, mg_h) * h : 0;
+            cp[u] = d.blue ? chirp[k] : C2<T>{T(1), T(0)};
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + u * kFftThreads;
+            if (e >= nf * h) continue;
+            const int f = udiv(e, mg_h), k = e - f * h;
+            const C2<T> x = ldc(buf + f * lbufp + pad(k));
+            const C2<T> r = d.blue ? cmul(cp[u], cconj(x)) : x;
+            const C2<T> g = {scale * r.x, -scale * r.y};
+            *reinterpret_cast<C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k) = g;
+        }
     }
 }
 
@@ -516,14 +557,28 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
     // 1. z_k = g_{2k} + i g_{2k+1}; Bluestein: times the chirp, zero-padded to L
     const int span = d.blue ? d.L : h;
     const unsigned mg_span = div_magic(span);
-    for (int e = threadIdx.x; e < nf * span; e += kFftThreads) {
-        int f = udiv(e, mg_span), k = e - f * span;
-        C2<T> z = {T(0), T(0)};
-        if (k < h) {
-            z = *reinterpret_cast<const C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k);
-            if (d.blue) z = cmul(z, chirp[k]);
+    for (int e0 = threadIdx.x; e0 < nf * span; e0 += kU * kFftThreads) {
+        C2<T> z[kU], cp[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + u * kFftThreads;
+            z[u] = C2<T>{T(0), T(0)};
+            cp[u] = C2<T>{T(1), T(0)};
+            if (e < nf * span) {
+                const int f = udiv(e, mg_span), k = e - f * span;
+                if (k < h) {
+                    z[u] = *reinterpret_cast<const C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k);
+                    if (d.blue) cp[u] = chirp[k];
+                }
+            }
         }
-        stc(buf + f * lbufp + pad(k), z);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + u * kFftThreads;
+            if (e >= nf * span) continue;
+            const int f = udiv(e, mg_span), k = e - f * span;
+            stc(buf + f * lbufp + pad(k), d.blue ? cmul(z[u], cp[u]) : z[u]);
+        }
     }
     __syncthreads();
     dft_h<T, CAP, TWL>(buf_off, d, a.passes, nf, W, bhat);
@@ -531,17 +586,37 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
     const T scale = a.adjoint ? T(1) : T(1.0 / d.n);
     C2<T> *four = (C2<T> *)a.out + d.four_off;
     const unsigned mg_nf = div_magic(nf);
-    for (int e = threadIdx.x; e < nf * (M + 1); e += kFftThreads) {
-        int m = udiv(e, mg_nf), f = e - m * nf;
-        const LdsC2<T> *s = buf + f * lbufp;
-        C2<T> zm = dft_out(s, d, chirp, m);
-        C2<T> zc = cconj(dft_out(s, d, chirp, m == 0 ? 0 : h - m));
-        C2<T> A = cadd(zm, zc), B = csub(zm, zc);
-        C2<T> t = cmul(post[m], B);
-        C2<T> y = {T(0.5) * (A.x + t.y), T(0.5) * (A.y - t.x)};
-        T fac = (a.adjoint && m > 0) ? T(2) : T(1);
-        y = {y.x * scale * fac, m == 0 ? T(0) : y.y * scale * fac};
-        four[(int64_t)m * a.nfld + f0 + f] = y;
+    const int nout = nf * (M + 1);
+    for (int e0 = threadIdx.x; e0 < nout; e0 += kU * kFftThreads) {
+        C2<T> pm[kU], cm[kU], ch[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + u * kFftThreads;
+            const int m = e < nout ? udiv(e, mg_nf) : 0;
+            pm[u] = post[m];
+            cm[u] = C2<T>{T(1), T(0)};
+            ch[u] = C2<T>{T(1), T(0)};
+            if (d.blue) {
+                cm[u] = chirp[m];
+                ch[u] = chirp[m == 0 ? 0 : h - m];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int e = e0 + u * kFftThreads;
+            if (e >= nout) continue;
+            const int m = udiv(e, mg_nf), f = e - m * nf;
+            const LdsC2<T> *sl = buf + f * lbufp;
+            const C2<T> xm = ldc(sl + pad(m)), xc = ldc(sl + pad(m == 0 ? 0 : h - m));
+            const C2<T> zm = d.blue ? cmul(cm[u], cconj(xm)) : xm;
+            const C2<T> zc = cconj(d.blue ? cmul(ch[u], cconj(xc)) : xc);
+            C2<T> A = cadd(zm, zc), B = csub(zm, zc);
+            C2<T> t = cmul(pm[u], B);
+            C2<T> y = {T(0.5) * (A.x + t.y), T(0.5) * (A.y - t.x)};
+            T fac = (a.adjoint && m > 0) ? T(2) : T(1);
+            y = {y.x * scale * fac, m == 0 ? T(0) : y.y * scale * fac};
+            four[(int64_t)m * a.nfld + f0 + f] = y;
+        }
     }
 }
 
