@@ -7,7 +7,7 @@
 // mixed-radix FFT (radices 8, 4, 2, 3, 5, 7) held in LDS, run in place: each
 // pass reads its butterflies into registers, synchronises, then writes.
 // Lengths with a prime factor above 7 go through Bluestein's chirp
-// convolution at a 7-smooth length L >= 2h - 1, with the filter spectrum
+// convolution at a length L = 2^a 3^b >= 2h - 1, with the filter spectrum
 // precomputed per ring length at plan time.  Only the kept wavenumbers
 // m <= M_j are read or written; they live in the Fourier workspace laid out
 // [ring][m][field], so a block's loads and stores are runs over fields.
@@ -72,6 +72,10 @@ template <typename T>
 using LdsC2 = __attribute__((address_space(3))) C2<T>;
 template <typename T>
 __device__ inline LdsC2<T> *lds_c2() { return (LdsC2<T> *)(__attribute__((address_space(3))) unsigned char *)fft_smem; }
+// LDS byte addressing for the Stockham passes: element r of a butterfly sits
+// at base + r * stride, formed with one 24-bit multiply-add per element.
+typedef __attribute__((address_space(3))) unsigned char LdsByte;
+
 // One complex value in or out of LDS as a single 2-element access.
 template <typename T>
 __device__ inline C2<T> ldc(const LdsC2<T> *p)
@@ -85,6 +89,16 @@ __device__ inline void stc(LdsC2<T> *p, C2<T> v)
 {
     typedef T V2 __attribute__((ext_vector_type(2)));
     *(__attribute__((address_space(3))) V2 *)p = V2{v.x, v.y};
+}
+template <typename T>
+__device__ inline C2<T> ldb(unsigned a)
+{
+    return ldc((const LdsC2<T> *)((LdsByte *)fft_smem + a));
+}
+template <typename T>
+__device__ inline void stb(unsigned a, C2<T> v)
+{
+    stc((LdsC2<T> *)((LdsByte *)fft_smem + a), v);
 }
 
 struct FftArgs {
@@ -245,9 +259,6 @@ constexpr int kU = 4;
 // times the LDS capacity).  magic 0 stands for d = 1.
 __device__ inline int udiv(int a, unsigned magic) { return magic ? (int)__umulhi((unsigned)a, magic) : a; }
 
-// LDS slot index with one pad entry per 8 complex values: the strided writes
-// of the first Stockham passes then spread over the banks.
-__device__ inline int pad(int i) { return i + (i >> 3); }
 
 // The table reads behind the twiddle powers of one butterfly: w = W[t1]
 // (w = exp(-2 pi i k / (Ns R))) and, for radix 9 and 16, w^3 or w^4.
@@ -290,8 +301,9 @@ __device__ inline void twiddle_powers(C2<T> *tw, C2<T> w1, C2<T> w2nd)
 // One in-place Stockham pass of radix R over nf fields of length L in LDS:
 // every thread reads all of its butterflies into registers, the block
 // synchronises, then each butterfly is twiddled, transformed and written.
-// BHAT (the last pass of Bluestein's first FFT): each output X_o is replaced
-// by conj(X_o bhat_o), the pointwise step of the chirp convolution.
+// BHAT (the first pass of Bluestein's second FFT, where Ns = 1): each input
+// X_i is first replaced by conj(X_i bhat_i), the pointwise step of the chirp
+// convolution.
 template <typename T>
 using GlobalC2 = const __attribute__((address_space(1))) C2<T>;
 
@@ -299,10 +311,11 @@ template <typename T, int R, int CAP, bool BHAT, typename WPtr>
 __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lbufp, int nf, PassDesc pd, WPtr W,
                                                              GlobalC2<T> *bhat)
 {
-    LdsC2<T> *buf = lds_c2<T>() + buf_off;
     constexpr int NB = (CAP / R + kFftThreads - 1) / kFftThreads;
     constexpr int C2ND = twiddle_step2<R>();
+    constexpr unsigned CB = sizeof(C2<T>);
     const int nbf = pd.nbf, total = nf * nbf, Ns = pd.Ns;
+    const unsigned srd = nbf * CB, swr = Ns * CB;  // byte strides of a butterfly's reads and writes
     C2<T> v[NB][R];
     C2<T> w1[NB], w2[NB];  // twiddle table values, fetched before the barrier
     int fo[NB], qk[NB][2];
@@ -312,7 +325,7 @@ __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lb
         if (e < total) {
             int f = udiv(e, pd.mg_nbf), j = e - f * nbf;
             int q = udiv(j, pd.mg_ns), k = j - q * Ns;
-            fo[b] = f * lbufp;
+            fo[b] = buf_off + f * lbufp;
             qk[b][0] = q;
             qk[b][1] = k;
             if (Ns > 1) {
@@ -320,14 +333,15 @@ __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lb
                 w1[b] = C2<T>{W[t1].x, W[t1].y};
                 if constexpr (C2ND > 0) w2[b] = C2<T>{W[C2ND * t1].x, W[C2ND * t1].y};
             }
-            const LdsC2<T> *src = buf + fo[b];
-            if (pd.nbf9) {
-                const LdsC2<T> *s0 = src + pad(j);
+            const unsigned a0 = (unsigned)(fo[b] + j) * CB;
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[b][r] = ldc(s0 + r * pd.nbf9);
-            } else {
+            for (int r = 0; r < R; ++r) v[b][r] = ldb<T>(a0 + __umul24((unsigned)r, srd));
+            if constexpr (BHAT) {
+                // first pass of Bluestein's second FFT (Ns = 1): its inputs
+                // are conj(X_i bhat_i), X the first FFT's output
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[b][r] = ldc(src + pad(j + r * nbf));
+                for (int r = 0; r < R; ++r)
+                    v[b][r] = cconj(cmul(v[b][r], C2<T>{bhat[j + r * nbf].x, bhat[j + r * nbf].y}));
             }
         }
     }
@@ -345,22 +359,9 @@ __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lb
                 for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r]);
             }
             dft_reg<T, R>(v[b]);
-            if constexpr (BHAT) {
+            const unsigned a0 = (unsigned)(fo[b] + base) * CB;
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int o = base + r * Ns;
-                    v[b][r] = cconj(cmul(v[b][r], C2<T>{bhat[o].x, bhat[o].y}));
-                }
-            }
-            LdsC2<T> *dst = buf + fo[b];
-            if (pd.ns9) {
-                LdsC2<T> *d0 = dst + pad(base);
-#pragma unroll
-                for (int r = 0; r < R; ++r) stc(d0 + r * pd.ns9, v[b][r]);
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r) stc(dst + pad(base + r * Ns), v[b][r]);
-            }
+            for (int r = 0; r < R; ++r) stb<T>(a0 + __umul24((unsigned)r, swr), v[b][r]);
         }
     }
     __syncthreads();
@@ -397,9 +398,10 @@ __device__ inline void pass_dispatch(int buf_off, int lbufp, int nf, const PassD
 
 // Length-h forward DFT of the h values at the start of each field slot.
 // Plain: a Stockham FFT of length h.  Bluestein: the input must already be
-// multiplied by the chirp and zero-padded to L; the first FFT's last pass
-// applies the filter (conj(X bhat)), the second FFT leaves conj(conv), and the
-// caller multiplies by the chirp when reading the first h outputs.
+// multiplied by the chirp and zero-padded to L; the second FFT's first pass
+// applies the filter (conj(X bhat)) to the first FFT's output, the second FFT
+// leaves conj(conv), and the caller multiplies by the chirp when reading the
+// first h outputs.
 template <typename T, int CAP, bool TWL>
 __device__ void dft_h(int buf_off, const RingDesc &d, const PassDesc *passes, int nf, const C2<T> *W,
                       const C2<T> *bhat)
@@ -407,15 +409,15 @@ __device__ void dft_h(int buf_off, const RingDesc &d, const PassDesc *passes, in
     const PassDesc *ps = passes + d.pass_off;
     for (int s = 0; s < d.nrad; ++s) {
         const PassDesc pd = ps[s];
-        if (d.blue && s == d.nrad - 1)
-            pass_dispatch<T, CAP, TWL, true>(buf_off, d.lbufp, nf, pd, W, bhat);
-        else
-            pass_dispatch<T, CAP, TWL, false>(buf_off, d.lbufp, nf, pd, W, bhat);
+        pass_dispatch<T, CAP, TWL, false>(buf_off, d.lbufp, nf, pd, W, bhat);
     }
     if (d.blue)
         for (int s = 0; s < d.nrad; ++s) {
             const PassDesc pd = ps[s];
-            pass_dispatch<T, CAP, TWL, false>(buf_off, d.lbufp, nf, pd, W, bhat);
+            if (s == 0)
+                pass_dispatch<T, CAP, TWL, true>(buf_off, d.lbufp, nf, pd, W, bhat);
+            else
+                pass_dispatch<T, CAP, TWL, false>(buf_off, d.lbufp, nf, pd, W, bhat);
         }
 }
 
@@ -493,8 +495,8 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
                 y0 = {y0.x * facpos, y0.y * facpos};
             y1 = {y1.x * facpos, y1.y * facpos};
             LdsC2<T> *sl = buf + ff[u] * lbufp;
-            if (m != 0 && m != h - m) stc(sl + pad(h - m), zprime(y1, y0, ph[u], ch[u]));
-            stc(sl + pad(m), zprime(y0, y1, pm[u], cm[u]));
+            if (m != 0 && m != h - m) stc(sl + (h - m), zprime(y1, y0, ph[u], ch[u]));
+            stc(sl + m, zprime(y0, y1, pm[u], cm[u]));
         }
     }
     if (d.blue) {
@@ -502,7 +504,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
         const unsigned mg_z = div_magic(zl);
         for (int e = threadIdx.x; e < nf * zl; e += kFftThreads) {
             int f = udiv(e, mg_z), k = h + e - f * zl;
-            stc(buf + f * lbufp + pad(k), C2<T>{T(0), T(0)});
+            stc(buf + f * lbufp + k, C2<T>{T(0), T(0)});
         }
     }
     __syncthreads();
@@ -525,7 +527,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
             const int e = e0 + u * kFftThreads;
             if (e >= nf * h) continue;
             const int f = udiv(e, mg_h), k = e - f * h;
-            const C2<T> x = ldc(buf + f * lbufp + pad(k));
+            const C2<T> x = ldc(buf + f * lbufp + k);
             const C2<T> r = d.blue ? cmul(cp[u], cconj(x)) : x;
             const C2<T> g = {scale * r.x, -scale * r.y};
             *reinterpret_cast<C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k) = g;
@@ -577,7 +579,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
             const int e = e0 + u * kFftThreads;
             if (e >= nf * span) continue;
             const int f = udiv(e, mg_span), k = e - f * span;
-            stc(buf + f * lbufp + pad(k), d.blue ? cmul(z[u], cp[u]) : z[u]);
+            stc(buf + f * lbufp + k, d.blue ? cmul(z[u], cp[u]) : z[u]);
         }
     }
     __syncthreads();
@@ -607,7 +609,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
             if (e >= nout) continue;
             const int m = udiv(e, mg_nf), f = e - m * nf;
             const LdsC2<T> *sl = buf + f * lbufp;
-            const C2<T> xm = ldc(sl + pad(m)), xc = ldc(sl + pad(m == 0 ? 0 : h - m));
+            const C2<T> xm = ldc(sl + m), xc = ldc(sl + (m == 0 ? 0 : h - m));
             const C2<T> zm = d.blue ? cmul(cm[u], cconj(xm)) : xm;
             const C2<T> zc = cconj(d.blue ? cmul(ch[u], cconj(xc)) : xc);
             C2<T> A = cadd(zm, zc), B = csub(zm, zc);
@@ -632,7 +634,7 @@ bool check_fft(const Plan &p, int cap)
     size_t celem = 2 * sizeof(T);
     for (const RingDesc &d : p.rings) {
         if (d.lbuf > cap || d.L > d.lbuf || d.h + 1 > d.lbuf || d.M >= d.h) SHTX_FFT_FAIL;
-        if (d.lbufp < d.lbuf + (d.lbuf - 1) / 8 + 1) SHTX_FFT_FAIL;  // pad(lbuf - 1) < lbufp
+        if (d.lbufp < d.lbuf) SHTX_FFT_FAIL;
         if ((size_t)(d.fb * d.lbufp + (p.fft_tw_lds ? d.L : 0)) * celem > (size_t)p.fft_lds_bytes) SHTX_FFT_FAIL;
         if (d.tw_off < 0 || d.tw_off + d.L > p.twid_elems) SHTX_FFT_FAIL;
         if (d.post_off < 0 || d.post_off + d.h + 1 > p.twid_elems) SHTX_FFT_FAIL;
@@ -652,8 +654,6 @@ bool check_fft(const Plan &p, int cap)
             const PassDesc &pd = p.passes[d.pass_off + s];
             if (pd.R != R || pd.Ns != prod || pd.nbf * R != d.L || pd.tstep * prod * R != d.L) SHTX_FFT_FAIL;
             if (pd.mg_nbf != div_magic(pd.nbf) || pd.mg_ns != div_magic(pd.Ns)) SHTX_FFT_FAIL;
-            if (pd.nbf9 != (pd.nbf % 8 ? 0 : pd.nbf / 8 * 9) || pd.ns9 != (pd.Ns % 8 ? 0 : pd.Ns / 8 * 9))
-                SHTX_FFT_FAIL;
             // twiddle reads W[c k tstep] (c = 1, and 3 or 4 for radix 9 or 16), k < Ns
             if (prod > 1 && (int64_t)(R == 16 ? 4 : R == 9 ? 3 : 1) * (prod - 1) * pd.tstep >= d.L) SHTX_FFT_FAIL;
             prod *= R;

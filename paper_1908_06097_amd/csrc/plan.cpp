@@ -256,15 +256,17 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
             lp.L = h;
             lp.blue = 0;
         } else {
-            // Bluestein length: the smallest 2^a 3^b >= 2h - 1 (radix-8/4/2/3
-            // passes only, the cheapest butterflies)
+            // Bluestein length: the smallest 2^a 3^b >= 2h - 1 with 9 | L
+            // (radix-16/9 passes; the leading radix-9 passes keep the
+            // power-of-two passes' LDS writes off a single bank)
             int L = 2 * h - 1;
-            auto is23 = [](int x) {
+            auto ok23 = [](int x) {
+                int threes = 0;
                 while (x % 2 == 0) x /= 2;
-                while (x % 3 == 0) x /= 3;
-                return x == 1;
+                while (x % 3 == 0) x /= 3, ++threes;
+                return x == 1 && threes >= 2;
             };
-            while (!is23(L)) ++L;
+            while (!ok23(L)) ++L;
             lp.L = L;
             lp.blue = 1;
         }
@@ -280,8 +282,6 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
             q.tstep = lp.L / (Ns * q.R);
             q.mg_nbf = div_magic(q.nbf);
             q.mg_ns = div_magic(Ns);
-            q.nbf9 = q.nbf % 8 == 0 ? q.nbf / 8 * 9 : 0;
-            q.ns9 = Ns % 8 == 0 ? Ns / 8 * 9 : 0;
             p.passes.push_back(q);
         }
         auto push = [&](long double re, long double im) {
@@ -336,7 +336,7 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         d.radcode = 0;
         for (int r = 0; r < d.nrad; ++r) d.radcode |= (unsigned long long)lp.rad[r] << (5 * r);
         d.lbuf = std::max(d.L, d.h + 1);
-        d.lbufp = d.lbuf + d.lbuf / 8 + 1;
+        d.lbufp = d.lbuf;
         d.fb = std::max(1, std::min(F, cap / d.lbuf));
         d.tw_off = lp.tw;
         d.post_off = lp.post;

@@ -49,7 +49,7 @@ struct RingDesc {
     int blue;     // 1 if the length-h DFT goes through Bluestein's convolution
     int fb;       // fields per FFT block for this ring
     int lbuf;     // complex values per field slot: max(L, h + 1)
-    int lbufp;    // LDS entries per field slot with one pad per 8 values
+    int lbufp;    // LDS entries per field slot
     int pass_off; // first PassDesc of this ring length's Stockham passes
     unsigned long long radcode;  // radix of pass s in bits [5s, 5s + 5)
     int64_t tw_off;     // W_L[k] = exp(-2 pi i k / L), k < L
@@ -70,8 +70,6 @@ struct PassDesc {
     int nbf;        // butterflies per field: L / R
     int tstep;      // twiddle table stride of the butterfly index: L / (Ns R)
     unsigned mg_nbf, mg_ns;
-    int nbf9;       // padded read stride nbf * 9 / 8 when 8 | nbf, else 0
-    int ns9;        // padded write stride Ns * 9 / 8 when 8 | Ns, else 0
 };
 
 __host__ __device__ inline unsigned div_magic(int d) { return d <= 1 ? 0u : 0xFFFFFFFFu / (unsigned)d + 1u; }
