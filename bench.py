@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fields", type=int, default=1)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the fixed default tile shapes instead of the plan-time autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one 1 GiB device-to-device copy, the reference kernel that "
                          "scales rocprofv3 FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -75,8 +77,9 @@ def tab_entries(plan):
     return tot
 
 
-def run_form(torch, shtx, wl, prec, steps, warmup, spec_host):
-    plan = shtx.Plan(wl.trunc, wl.grid, wl.nlat, wl.nfld, prec, nlon_full=wl.nlon_full, timing=True)
+def run_form(torch, shtx, wl, prec, steps, warmup, spec_host, autotune):
+    plan = shtx.Plan(wl.trunc, wl.grid, wl.nlat, wl.nfld, prec, nlon_full=wl.nlon_full, timing=True,
+                     autotune=autotune)
     spec = spec_host.to(plan.complex_dtype).cuda()
     grid = torch.empty((wl.nfld, plan.npts), dtype=plan.real_dtype, device="cuda")
     out = torch.empty_like(spec)
@@ -101,6 +104,12 @@ def run_form(torch, shtx, wl, prec, steps, warmup, spec_host):
         "legendre_flops": float(plan.info.legendre_flops),
     }
     return res
+
+
+def tiles_of(plan):
+    i = plan.info
+    return {"inverse_gemm": list(i.inv_tile), "direct_gemm": list(i.dir_tile), "fft_cap": int(i.fft_cap),
+            "chosen_by": ["default", "autotuner", "tune cache"][int(i.tuned)]}
 
 
 def roofline_for(res, prec):
@@ -194,7 +203,7 @@ def main():
     spec_host = torch.from_numpy(spec_np)
 
     print(f"[bench] headline form {args.prec}", file=sys.stderr, flush=True)
-    res = run_form(torch, shtx, wl, args.prec, args.steps, args.warmup, spec_host)
+    res = run_form(torch, shtx, wl, args.prec, args.steps, args.warmup, spec_host, not args.no_autotune)
     roof = roofline_for(res, args.prec)
     dom = max(roof, key=lambda k: roof[k]["ms"])
     d = roof[dom]
@@ -215,7 +224,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "trunc": wl.trunc, "grid": f"O{wl.nlat // 2}" if wl.grid == "octahedral"
                    else f"full {wl.nlat}x{wl.nlon_full}", "nlat": wl.nlat, "fields": wl.nfld,
-                   "legendre_form": args.prec, "fft_dtype": "f64" if args.prec == "fp64" else "f32"},
+                   "legendre_form": args.prec, "fft_dtype": "f64" if args.prec == "fp64" else "f32",
+                   "tiles": tiles_of(res["plan"])},
         "legendre_tflops": res["legendre_flops"] * 2 / (
             (res["kernel_ms"]["legendre_inverse_gemm"] + res["kernel_ms"]["legendre_direct_gemm"]) * 1e-3) / 1e12,
         "roofline": roofline,
@@ -234,10 +244,10 @@ def main():
     forms = {}
     for prec in [p for p in args.forms.split(",") if p and p != "none" and p != args.prec]:
         print(f"[bench] form {prec}", file=sys.stderr, flush=True)
-        r = run_form(torch, shtx, wl, prec, args.form_steps, 1, spec_host)
+        r = run_form(torch, shtx, wl, prec, args.form_steps, 1, spec_host, not args.no_autotune)
         rf = roofline_for(r, prec)
         forms[prec] = {"fields_per_s": r["fields_per_s"], "ms_per_step": r["ms_per_step"],
-                       "kernel_ms": r["kernel_ms"],
+                       "kernel_ms": r["kernel_ms"], "tiles": tiles_of(r["plan"]),
                        "legendre_frac": {k: rf[k]["frac"] for k in rf if k.startswith("legendre")}}
         if not args.no_cpu_baseline:
             forms[prec]["error_vs_oracle"] = errors_vs_oracle(torch, r, g_ref, b_ref, wl, args.cpu_fields)

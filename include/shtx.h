@@ -72,6 +72,15 @@ enum shtx_status {
 
 /* Flags for shtx_plan_create. */
 #define SHTX_FLAG_GRAPH 1u /* replay each transform as a captured hipGraph */
+/* Tile autotuning: plan creation times every candidate tile shape of the
+ * two Legendre GEMM launches and every candidate ring-FFT blocking on the
+ * plan's own shape (zero-filled scratch inputs) and keeps the fastest; the
+ * choice is reported in shtx_info.  If the environment variable
+ * SHTX_TUNE_CACHE names a file, choices are looked up there first and
+ * appended after timing, one JSON object per line, keyed by GPU
+ * architecture, truncation, grid, latitudes, fields, precision and a hash of
+ * the kernel sources.  Without the flag each precision uses fixed shapes. */
+#define SHTX_FLAG_AUTOTUNE 4u
 
 typedef struct {
     int32_t trunc, nlat, nfld, prec, grid;
@@ -83,6 +92,10 @@ typedef struct {
     size_t workspace_bytes; /* Fourier workspace and FFT tables */
     double legendre_flops;  /* algorithmic Legendre flops of one transform, all fields */
     double plan_seconds;    /* wall time of shtx_plan_create */
+    int32_t inv_tile[2];    /* rows x columns of the inverse-shaped GEMM tiles */
+    int32_t dir_tile[2];    /* rows x columns of the direct-shaped GEMM tiles */
+    int32_t fft_cap;        /* LDS complex values per ring-FFT block (fields per block = cap / ring slot) */
+    int32_t tuned;          /* 0 default shapes, 1 timed at plan creation, 2 read from the tune cache */
 } shtx_info;
 
 /* Create a plan for triangular truncation `trunc` on `nlat` Gaussian
@@ -101,6 +114,22 @@ int shtx_plan_info(shtx_plan p, shtx_info *out);
  * touching any device.  Returns what shtx_plan_create would return for a
  * shape problem (SHTX_EINVAL / SHTX_EUNSUPPORTED) or SHTX_OK. */
 int shtx_plan_check(int trunc, int grid, int nlat, int nlon_full, int nfld, int prec, shtx_info *out);
+
+/* Like shtx_plan_check, with explicit GEMM tile shapes (rows x columns of
+ * the inverse- and direct-shaped launches; one of the shapes the autotuner
+ * considers for the precision) and ring-FFT blocking `fft_cap` (LDS complex
+ * values per block, 1 .. 6144).  A shape without a kernel instantiation is
+ * SHTX_EUNSUPPORTED; fft_cap out of range is SHTX_EINVAL. */
+int shtx_plan_check_shapes(int trunc, int grid, int nlat, int nlon_full, int nfld, int prec, int inv_bm,
+                           int inv_bn, int dir_bm, int dir_bn, int fft_cap, shtx_info *out);
+
+/* Pin the GEMM tile shapes and ring-FFT blocking of an existing plan (for
+ * example shapes chosen by an external tuner), with the same meaning and
+ * checks as shtx_plan_check_shapes.  Synchronises the device first; no
+ * transform of this plan may be in flight on another thread.  On error the
+ * plan keeps working only if the return is SHTX_EINVAL or SHTX_EUNSUPPORTED
+ * (nothing was changed). */
+int shtx_plan_set_shapes(shtx_plan p, int inv_bm, int inv_bn, int dir_bm, int dir_bn, int fft_cap);
 
 /* Host copies of plan geometry: nlon[nlat] ring lengths. */
 int shtx_plan_ring_lengths(shtx_plan p, int32_t *nlon_host);

@@ -24,10 +24,11 @@ GRIDS = {"full": 0, "octahedral": 1}
 PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 FLAG_GRAPH = 1
 FLAG_TIMING = 2
+FLAG_AUTOTUNE = 4
 
 _lib = None
 
-_EXPORTS = ("shtx_plan_create", "shtx_plan_check", "shtx_plan_info", "shtx_plan_ring_lengths", "shtx_plan_nodes",
+_EXPORTS = ("shtx_plan_create", "shtx_plan_check", "shtx_plan_check_shapes", "shtx_plan_set_shapes", "shtx_plan_info", "shtx_plan_ring_lengths", "shtx_plan_nodes",
             "shtx_plan_legendre", "shtx_inv_trans", "shtx_dir_trans", "shtx_inv_trans_adj",
             "shtx_dir_trans_adj", "shtx_timing_reset", "shtx_timing_read", "shtx_plan_destroy",
             "shtx_strerror")
@@ -42,7 +43,9 @@ class Info(ctypes.Structure):
                 ("prec", ctypes.c_int32), ("grid", ctypes.c_int32), ("max_nlon", ctypes.c_int32),
                 ("nspec", ctypes.c_int64), ("npts", ctypes.c_int64), ("nfour", ctypes.c_int64),
                 ("table_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
-                ("legendre_flops", ctypes.c_double), ("plan_seconds", ctypes.c_double)]
+                ("legendre_flops", ctypes.c_double), ("plan_seconds", ctypes.c_double),
+                ("inv_tile", ctypes.c_int32 * 2), ("dir_tile", ctypes.c_int32 * 2), ("fft_cap", ctypes.c_int32),
+                ("tuned", ctypes.c_int32)]
 
 
 def load_library():
@@ -57,6 +60,8 @@ def load_library():
     lib.shtx_plan_create.argtypes = [ctypes.POINTER(vp), i32, i32, i32, i32, i32, i32, u32, vp]
     lib.shtx_plan_info.argtypes = [vp, ctypes.POINTER(Info)]
     lib.shtx_plan_check.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.POINTER(Info)]
+    lib.shtx_plan_check_shapes.argtypes = [i32] * 11 + [ctypes.POINTER(Info)]
+    lib.shtx_plan_set_shapes.argtypes = [vp] + [i32] * 5
     lib.shtx_plan_ring_lengths.argtypes = [vp, ctypes.c_void_p]
     lib.shtx_plan_nodes.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
     lib.shtx_plan_legendre.argtypes = [vp, i32, ctypes.c_void_p]
@@ -84,6 +89,15 @@ def plan_check(trunc, grid="octahedral", nlat=None, nfld=1, prec="fp32", nlon_fu
     return rc, info
 
 
+def plan_check_shapes(trunc, grid, nlat, nfld, prec, inv_tile, dir_tile, fft_cap, nlon_full=0):
+    """Host-only dry run with explicit GEMM tile shapes and FFT blocking."""
+    lib = load_library()
+    info = Info()
+    rc = lib.shtx_plan_check_shapes(trunc, GRIDS[grid], nlat, nlon_full, nfld, PRECS[prec], inv_tile[0],
+                                    inv_tile[1], dir_tile[0], dir_tile[1], fft_cap, ctypes.byref(info))
+    return rc, info
+
+
 def _check(rc, what):
     if rc < 0:
         raise ShtxError(f"{what} failed: {load_library().shtx_strerror(rc).decode()} ({rc})")
@@ -95,7 +109,7 @@ class Plan:
     the current CUDA/HIP device.  Transforms run on torch's current stream."""
 
     def __init__(self, trunc, grid="octahedral", nlat=None, nfld=1, prec="fp32", nlon_full=0,
-                 graph=False, timing=False):
+                 graph=False, timing=False, autotune=False):
         import torch
         if not torch.cuda.is_available():
             raise ShtxError("libshtx needs a ROCm GPU; no CPU fallback exists")
@@ -103,7 +117,7 @@ class Plan:
         if nlat is None:
             nlat = 2 * (trunc + 1)
         self.trunc, self.grid, self.nlat, self.nfld, self.prec = trunc, grid, nlat, nfld, prec
-        flags = (FLAG_GRAPH if graph else 0) | (FLAG_TIMING if timing else 0)
+        flags = (FLAG_GRAPH if graph else 0) | (FLAG_TIMING if timing else 0) | (FLAG_AUTOTUNE if autotune else 0)
         h = ctypes.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream
         _check(lib.shtx_plan_create(ctypes.byref(h), trunc, GRIDS[grid], nlat, nlon_full, nfld,
@@ -115,6 +129,12 @@ class Plan:
         self.npts = int(self.info.npts)
         self.real_dtype = torch.float64 if prec == "fp64" else torch.float32
         self.complex_dtype = torch.complex128 if prec == "fp64" else torch.complex64
+
+    def set_shapes(self, inv_tile, dir_tile, fft_cap):
+        """Pin the GEMM tile shapes and FFT blocking (see shtx_plan_set_shapes)."""
+        _check(load_library().shtx_plan_set_shapes(self._h, inv_tile[0], inv_tile[1], dir_tile[0], dir_tile[1],
+                                                   fft_cap), "shtx_plan_set_shapes")
+        _check(load_library().shtx_plan_info(self._h, ctypes.byref(self.info)), "shtx_plan_info")
 
     # -- geometry and tables --------------------------------------------------
     def ring_lengths(self):

@@ -4,6 +4,7 @@ Every source is compiled for gfx950 only, with packed-FP32 instructions
 disabled, then linked into one shared library next to this file.
 """
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -12,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libshtx.so")
-SOURCES = ["plan.cpp", "capi.cpp", "k_tables.hip", "k_gemm.hip", "k_fft.hip"]
+SOURCES = ["plan.cpp", "capi.cpp", "autotune.cpp", "k_tables.hip", "k_gemm.hip", "k_fft.hip"]
 BUILD = os.path.join(HERE, "_build")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-I", INCLUDE,
@@ -20,10 +21,19 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-I", INCLUDE,
          "-Wall", "-Wno-unused-function"]
 
 
-def _compile(src, verbose):
+def build_id():
+    """Hash of every library source: keys the autotuner's cache to the kernels."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src, verbose, bid):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"]
-    cmd = ["hipcc", *lang, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *lang, *FLAGS, f'-DSHTX_BUILD_ID="{bid}"', "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -36,8 +46,9 @@ def _compile(src, verbose):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    bid = build_id()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda s: _compile(s, verbose, bid), SOURCES))
     cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -161,6 +161,12 @@ static void fill_info(const Plan &p, shtx_info *o)
     o->workspace_bytes = p.workspace_bytes;
     o->legendre_flops = p.legendre_flops;
     o->plan_seconds = p.plan_seconds;
+    o->inv_tile[0] = p.inv_bm;
+    o->inv_tile[1] = p.inv_bn;
+    o->dir_tile[0] = p.dir_bm;
+    o->dir_tile[1] = p.dir_bn;
+    o->fft_cap = p.fft_cap;
+    o->tuned = p.tuned;
 }
 
 int shtx_plan_info(shtx_plan h, shtx_info *o)
@@ -174,6 +180,25 @@ int shtx_plan_check(int trunc, int grid, int nlat, int nlon_full, int nfld, int 
 {
     Plan p;
     int rc = shtx::plan_layout(p, trunc, grid, nlat, nlon_full, nfld, prec, 0);
+    if (rc != SHTX_OK) return rc;
+    if (!shtx::gemm_shapes_ok(p) || !shtx::fft_shapes_ok(p)) return SHTX_EUNSUPPORTED;
+    if (out) fill_info(p, out);
+    return SHTX_OK;
+}
+
+int shtx_plan_check_shapes(int trunc, int grid, int nlat, int nlon_full, int nfld, int prec, int inv_bm, int inv_bn,
+                           int dir_bm, int dir_bn, int fft_cap, shtx_info *out)
+{
+    Plan p;
+    int rc = shtx::plan_layout(p, trunc, grid, nlat, nlon_full, nfld, prec, 0);
+    if (rc != SHTX_OK) return rc;
+    p.inv_bm = inv_bm;
+    p.inv_bn = inv_bn;
+    p.dir_bm = dir_bm;
+    p.dir_bn = dir_bn;
+    rc = shtx::gemm_work_lists(p);
+    if (rc != SHTX_OK) return rc;
+    rc = shtx::fft_blocking(p, fft_cap);
     if (rc != SHTX_OK) return rc;
     if (!shtx::gemm_shapes_ok(p) || !shtx::fft_shapes_ok(p)) return SHTX_EUNSUPPORTED;
     if (out) fill_info(p, out);
@@ -285,6 +310,21 @@ int shtx_timing_read(shtx_plan h, double *ms_sum, int32_t *count)
         if (count) count[k] = cnt[k];
     }
     return SHTX_OK;
+}
+
+int shtx_plan_set_shapes(shtx_plan h, int inv_bm, int inv_bn, int dir_bm, int dir_bn, int fft_cap)
+{
+    if (!h) return SHTX_EINVAL;
+    Plan &p = h->p;
+    // earlier transforms may still read the old work lists
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_status(e);
+    for (auto &g : p.graphs)
+        if (g.exec) {
+            (void)hipGraphExecDestroy(g.exec);
+            g = Plan::GraphEntry{};
+        }
+    return shtx::apply_shapes(p, inv_bm, inv_bn, dir_bm, dir_bn, fft_cap);
 }
 
 int shtx_plan_destroy(shtx_plan h)

@@ -702,50 +702,96 @@ bool check_items_impl(const Plan &p, const std::vector<GemmItem> &items, bool in
     return true;
 }
 
+
+template <typename T, int BK, bool INV>
+hipError_t launch_mfma(const Plan &p, const GemmArgs &a, int bm, int bn, hipStream_t s)
+{
+    const std::vector<GemmItem> &items = INV ? p.inv_items : p.dir_items;
+    const int grid = (int)items.size();
+    if (!check_items(p, items, INV, bm, bn, BK)) return hipErrorInvalidValue;
+#define SHTX_TILE(BM, BN)                                                  \
+    if (bm == BM && bn == BN) {                                            \
+        k_leg_mfma<T, BM, BN, BK, INV><<<grid, 256, 0, s>>>(a);            \
+        return hipGetLastError();                                          \
+    }
+    if constexpr (sizeof(T) == 4) {
+        SHTX_TILE(128, 128)
+        SHTX_TILE(64, 128)
+        SHTX_TILE(128, 64)
+    } else {
+        SHTX_TILE(64, 64)
+        SHTX_TILE(32, 64)
+        SHTX_TILE(64, 32)
+    }
+#undef SHTX_TILE
+    return hipErrorInvalidValue;
+}
+
+template <bool INV>
+hipError_t launch_bf16(const Plan &p, const GemmArgs &a, int bm, int bn, hipStream_t s)
+{
+    const std::vector<GemmItem> &items = INV ? p.inv_items : p.dir_items;
+    const int grid = (int)items.size();
+    if (!check_items(p, items, INV, bm, bn, 32)) return hipErrorInvalidValue;
+    if (bm == 128 && bn == 128)
+        k_leg_bf16x3<128, 128, 32, INV><<<grid, 256, 0, s>>>(a);
+    else if (bm == 64 && bn == 128)
+        k_leg_bf16x3<64, 128, 32, INV><<<grid, 256, 0, s>>>(a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 }  // namespace
+
+// Tile shapes with a kernel instantiation, the default first.
+int gemm_tile_candidates(int prec, int *bm, int *bn, int max)
+{
+    static const int f32[][2] = {{128, 128}, {64, 128}, {128, 64}};
+    static const int f64[][2] = {{64, 64}, {32, 64}, {64, 32}};
+    static const int b16[][2] = {{128, 128}, {64, 128}};
+    const int(*t)[2] = prec == SHTX_FP64 ? f64 : prec == SHTX_FP32 ? f32 : b16;
+    int n = prec == SHTX_BF16X3 ? 2 : 3;
+    for (int i = 0; i < n && i < max; ++i) {
+        bm[i] = t[i][0];
+        bn[i] = t[i][1];
+    }
+    return n;
+}
+
+bool gemm_tile_supported(int prec, int bm, int bn)
+{
+    int cbm[8], cbn[8];
+    int n = gemm_tile_candidates(prec, cbm, cbn, 8);
+    for (int i = 0; i < n; ++i)
+        if (cbm[i] == bm && cbn[i] == bn) return true;
+    return false;
+}
 
 bool gemm_shapes_ok(const Plan &p)
 {
     int bk = p.prec == SHTX_BF16X3 ? 32 : 16;
-    int bm = p.prec == SHTX_FP64 ? 64 : 128, bn = bm;
-    if (p.inv_bm != bm || p.inv_bn != bn || p.dir_bm != bm || p.dir_bn != bn) return false;
-    bool inv_ok = p.inv_items.empty() || check_items(p, p.inv_items, true, bm, bn, bk);
-    return inv_ok && check_items(p, p.dir_items, false, bm, bn, bk);
+    if (!gemm_tile_supported(p.prec, p.inv_bm, p.inv_bn) || !gemm_tile_supported(p.prec, p.dir_bm, p.dir_bn))
+        return false;
+    bool inv_ok = p.inv_items.empty() || check_items(p, p.inv_items, true, p.inv_bm, p.inv_bn, bk);
+    return inv_ok && check_items(p, p.dir_items, false, p.dir_bm, p.dir_bn, bk);
 }
 
 hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, hipStream_t s)
 {
     GemmArgs a = make_args(p, true, spec, four, false);
-    int grid = (int)p.inv_items.size();
-    if (grid == 0) return hipSuccess;
-    if (p.prec == SHTX_FP64) {
-        if (!check_items(p, p.inv_items, true, 64, 64, 16)) return hipErrorInvalidValue;
-        k_leg_mfma<double, 64, 64, 16, true><<<grid, 256, 0, s>>>(a);
-    } else if (p.prec == SHTX_FP32) {
-        if (!check_items(p, p.inv_items, true, 128, 128, 16)) return hipErrorInvalidValue;
-        k_leg_mfma<float, 128, 128, 16, true><<<grid, 256, 0, s>>>(a);
-    } else {
-        if (!check_items(p, p.inv_items, true, 128, 128, 32)) return hipErrorInvalidValue;
-        k_leg_bf16x3<128, 128, 32, true><<<grid, 256, 0, s>>>(a);
-    }
-    return hipGetLastError();
+    if (p.inv_items.empty()) return hipSuccess;
+    if (p.prec == SHTX_FP64) return launch_mfma<double, 16, true>(p, a, p.inv_bm, p.inv_bn, s);
+    if (p.prec == SHTX_FP32) return launch_mfma<float, 16, true>(p, a, p.inv_bm, p.inv_bn, s);
+    return launch_bf16<true>(p, a, p.inv_bm, p.inv_bn, s);
 }
 
 hipError_t launch_gemm_direct(const Plan &p, const void *four, void *spec, bool adjoint, hipStream_t s)
 {
     GemmArgs a = make_args(p, false, four, spec, adjoint);
-    int grid = (int)p.dir_items.size();
-    if (p.prec == SHTX_FP64) {
-        if (!check_items(p, p.dir_items, false, 64, 64, 16)) return hipErrorInvalidValue;
-        k_leg_mfma<double, 64, 64, 16, false><<<grid, 256, 0, s>>>(a);
-    } else if (p.prec == SHTX_FP32) {
-        if (!check_items(p, p.dir_items, false, 128, 128, 16)) return hipErrorInvalidValue;
-        k_leg_mfma<float, 128, 128, 16, false><<<grid, 256, 0, s>>>(a);
-    } else {
-        if (!check_items(p, p.dir_items, false, 128, 128, 32)) return hipErrorInvalidValue;
-        k_leg_bf16x3<128, 128, 32, false><<<grid, 256, 0, s>>>(a);
-    }
-    return hipGetLastError();
+    if (p.prec == SHTX_FP64) return launch_mfma<double, 16, false>(p, a, p.dir_bm, p.dir_bn, s);
+    if (p.prec == SHTX_FP32) return launch_mfma<float, 16, false>(p, a, p.dir_bm, p.dir_bn, s);
+    return launch_bf16<false>(p, a, p.dir_bm, p.dir_bn, s);
 }
 
 }  // namespace shtx

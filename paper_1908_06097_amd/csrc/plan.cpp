@@ -169,6 +169,72 @@ void free_plan(Plan &p)
         }                                                \
     } while (0)
 
+// FFT blocking: fields per block (at most `cap` complex values of LDS per
+// block), the XCD-segmented work list and the dynamic LDS size.
+int fft_blocking(Plan &p, int cap)
+{
+    const int F = p.nfld, maxcap = p.prec == SHTX_FP64 ? kFftCapF64 : kFftCapF32;
+    const size_t celem = p.prec == SHTX_FP64 ? 16 : 8;
+    if (cap < 1 || cap > maxcap) return SHTX_EINVAL;
+    int lds_elems = 0, lds_tw = 0;
+    std::vector<std::vector<FftItem>> fgroups;
+    std::vector<double> fcost;
+    for (int j = 0; j < p.nlat; ++j) {
+        RingDesc &d = p.rings[j];
+        if (d.lbuf > maxcap) return SHTX_EUNSUPPORTED;
+        d.fb = std::max(1, std::min(F, cap / d.lbuf));
+        lds_elems = std::max(lds_elems, d.fb * d.lbufp);
+        lds_tw = std::max(lds_tw, d.fb * d.lbufp + d.L);
+        std::vector<FftItem> g;
+        for (int f0 = 0; f0 < F; f0 += d.fb) g.push_back(FftItem{j, f0, std::min(d.fb, F - f0), 0});
+        fgroups.push_back(g);
+        fcost.push_back((double)F * d.L * (1 + d.blue) * std::log2((double)d.L + 1));
+    }
+    // twiddle tables go to LDS while two blocks still fit one CU's 160 KiB
+    p.fft_tw_lds = (size_t)lds_tw * celem <= 80 * 1024;
+    if (p.fft_tw_lds) lds_elems = lds_tw;
+    p.fft_lds_bytes = lds_elems * (int)celem;
+    p.fft_lds_max = lds_elems;
+    p.fft_cap = cap;
+    if (p.fft_lds_bytes > 160 * 1024) return SHTX_EUNSUPPORTED;
+    p.fft_items = layout_by_xcd(fgroups, fcost, FftItem{-1, 0, 0, 0});
+    return SHTX_OK;
+}
+
+// GEMM work lists for the plan's current tile shapes: every (m, row tile,
+// column tile), one XCD segment per group of tiles sharing an m.
+int gemm_work_lists(Plan &p)
+{
+    if (!gemm_tile_supported(p.prec, p.inv_bm, p.inv_bn) || !gemm_tile_supported(p.prec, p.dir_bm, p.dir_bn))
+        return SHTX_EUNSUPPORTED;
+    if (kTablePad % p.inv_bm || kTablePad % p.dir_bm) return SHTX_EUNSUPPORTED;
+    const int N = p.trunc, ncol = 2 * p.nfld;
+    std::vector<std::vector<GemmItem>> gi, gd;
+    std::vector<double> ci, cd;
+    for (int m = 0; m <= N; ++m) {
+        const MBlock &b = p.mb[m];
+        double cost = (double)std::max(b.R, 1) * (N - m + 1) * ncol;
+        std::vector<GemmItem> a, c;
+        int ntc_i = (ncol + p.inv_bn - 1) / p.inv_bn;
+        int ntr_i = (b.R + p.inv_bm - 1) / p.inv_bm;
+        for (int tr = 0; tr < ntr_i; ++tr)
+            for (int tc = 0; tc < ntc_i; ++tc) a.push_back(GemmItem{m, tr, tc, 0});
+        int ntc_d = (ncol + p.dir_bn - 1) / p.dir_bn;
+        int ntk_d = (b.K0 + p.dir_bm - 1) / p.dir_bm;
+        for (int tk = 0; tk < ntk_d; ++tk)
+            for (int tc = 0; tc < ntc_d; ++tc) c.push_back(GemmItem{m, tk, tc, 0});
+        if (!a.empty()) {
+            gi.push_back(a);
+            ci.push_back(cost);
+        }
+        gd.push_back(c);
+        cd.push_back(cost);
+    }
+    p.inv_items = layout_by_xcd(gi, ci, GemmItem{-1, 0, 0, 0});
+    p.dir_items = layout_by_xcd(gd, cd, GemmItem{-1, 0, 0, 0});
+    return SHTX_OK;
+}
+
 // Host part of plan construction: geometry, table layout, FFT length plans
 // and twiddle tables (kept on the host until uploaded), GEMM and FFT work
 // lists.  Touches no device state, so it can be checked on any machine.
@@ -320,9 +386,6 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
 
     p.rings.resize(nlat);
     int64_t goff = 0, foff = 0;
-    int lds_elems = 0;
-    std::vector<std::vector<FftItem>> fgroups;
-    std::vector<double> fcost;
     for (int j = 0; j < nlat; ++j) {
         RingDesc d{};
         const LenPlan &lp = lens[p.nlon[j]];
@@ -337,7 +400,6 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         for (int r = 0; r < d.nrad; ++r) d.radcode |= (unsigned long long)lp.rad[r] << (5 * r);
         d.lbuf = std::max(d.L, d.h + 1);
         d.lbufp = d.lbuf;
-        d.fb = std::max(1, std::min(F, cap / d.lbuf));
         d.tw_off = lp.tw;
         d.post_off = lp.post;
         d.chirp_off = lp.chirp;
@@ -348,54 +410,17 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         goff += d.n;
         foff += (int64_t)(d.M + 1) * F;
         p.rings[j] = d;
-        lds_elems = std::max(lds_elems, d.fb * d.lbufp);
-        std::vector<FftItem> g;
-        for (int f0 = 0; f0 < F; f0 += d.fb) g.push_back(FftItem{j, f0, std::min(d.fb, F - f0), 0});
-        fgroups.push_back(g);
-        fcost.push_back((double)F * d.L * (1 + d.blue) * std::log2((double)d.L + 1));
     }
     p.npts = goff;
     p.nfour = foff / F;
-    // twiddle tables go to LDS when every block still fits in 160 KiB with them
-    int lds_tw = 0;
-    for (const RingDesc &d : p.rings) lds_tw = std::max(lds_tw, d.fb * d.lbufp + d.L);
-    // (only while two blocks still fit one CU's 160 KiB)
-    p.fft_tw_lds = (size_t)lds_tw * celem <= 80 * 1024;
-    if (p.fft_tw_lds) lds_elems = lds_tw;
-    p.fft_lds_bytes = lds_elems * (int)celem;
-    p.fft_lds_max = lds_elems;
-    if (p.fft_lds_bytes > 160 * 1024) return SHTX_EUNSUPPORTED;
-    p.fft_items = layout_by_xcd(fgroups, fcost, FftItem{-1, 0, 0, 0});
+    if (p.nfour > INT32_MAX) return SHTX_EUNSUPPORTED;  // ring offsets are stored as int32 / nfld
+    int rc = fft_blocking(p, cap);
+    if (rc != SHTX_OK) return rc;
 
     // ---- GEMM work lists ----------------------------------------------------------
     gemm_tiles(prec, &p.inv_bm, &p.inv_bn, &p.dir_bm, &p.dir_bn);
-    if (kTablePad % p.inv_bm || kTablePad % p.dir_bm) return SHTX_EUNSUPPORTED;
-    {
-        std::vector<std::vector<GemmItem>> gi, gd;
-        std::vector<double> ci, cd;
-        int ncol = 2 * F;
-        for (int m = 0; m <= N; ++m) {
-            const MBlock &b = p.mb[m];
-            double cost = (double)std::max(b.R, 1) * (N - m + 1) * ncol;
-            std::vector<GemmItem> a, c;
-            int ntc_i = (ncol + p.inv_bn - 1) / p.inv_bn;
-            int ntr_i = (b.R + p.inv_bm - 1) / p.inv_bm;
-            for (int tr = 0; tr < ntr_i; ++tr)
-                for (int tc = 0; tc < ntc_i; ++tc) a.push_back(GemmItem{m, tr, tc, 0});
-            int ntc_d = (ncol + p.dir_bn - 1) / p.dir_bn;
-            int ntk_d = (b.K0 + p.dir_bm - 1) / p.dir_bm;
-            for (int tk = 0; tk < ntk_d; ++tk)
-                for (int tc = 0; tc < ntc_d; ++tc) c.push_back(GemmItem{m, tk, tc, 0});
-            if (!a.empty()) {
-                gi.push_back(a);
-                ci.push_back(cost);
-            }
-            gd.push_back(c);
-            cd.push_back(cost);
-        }
-        p.inv_items = layout_by_xcd(gi, ci, GemmItem{-1, 0, 0, 0});
-        p.dir_items = layout_by_xcd(gd, cd, GemmItem{-1, 0, 0, 0});
-    }
+    rc = gemm_work_lists(p);
+    if (rc != SHTX_OK) return rc;
 
     p.workspace_bytes += (size_t)p.nfour * F * celem;
     return SHTX_OK;
@@ -482,6 +507,11 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
     PLAN_TRY(upload(&p.d_dir_items, p.dir_items));
 
     PLAN_TRY(hipMalloc(&p.d_four, (size_t)p.nfour * nfld * celem));
+
+    if (flags & SHTX_FLAG_AUTOTUNE) {
+        int trc = autotune_plan(p, stream);
+        if (trc != SHTX_OK) return trc;
+    }
 
     if (flags & SHTX_FLAG_TIMING) {
         p.ev_start.resize(Plan::kMaxTimed);

@@ -104,6 +104,8 @@ struct Plan {
     std::vector<PassDesc> passes;
     int fft_lds_bytes = 0;
     int fft_lds_max = 0;  // complex entries of LDS the largest FFT block may use
+    int fft_cap = 0;      // LDS complex values per FFT block the blocking was made for
+    int tuned = 0;        // 0 default tiles, 1 timed by the autotuner, 2 from the tune cache
     bool fft_tw_lds = false;  // FFT blocks stage their twiddle table in LDS
 
     // Device memory.
@@ -164,8 +166,24 @@ bool gemm_shapes_ok(const Plan &p);
 bool fft_shapes_ok(const Plan &p);
 int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, int prec, unsigned flags);
 
-// GEMM tile sizes per precision (rows, columns) for each direction.
+// GEMM tile sizes per precision (rows, columns) for each direction: the
+// defaults, and whether a kernel instantiation exists for a shape.
 void gemm_tiles(int prec, int *inv_bm, int *inv_bn, int *dir_bm, int *dir_bn);
+bool gemm_tile_supported(int prec, int bm, int bn);
+// Candidate shapes the autotuner times (count returned, shapes in bm[], bn[]).
+int gemm_tile_candidates(int prec, int *bm, int *bn, int max);
+
+// Rebuild the FFT blocking (fields per block within `cap` LDS complex
+// values) and the GEMM work lists for the plan's current tile shapes.
+int fft_blocking(Plan &p, int cap);
+int gemm_work_lists(Plan &p);
+
+// Time the candidate GEMM tile shapes and FFT blockings on this plan and keep
+// the fastest (or take them from the tune cache); uploads the work lists.
+int autotune_plan(Plan &p, hipStream_t s);
+// Set the GEMM tile shapes and FFT blocking of a built plan (rebuilds and
+// uploads the work lists; the caller makes sure no transform is in flight).
+int apply_shapes(Plan &p, int inv_bm, int inv_bn, int dir_bm, int dir_bn, int fft_cap);
 
 // Host-side Bluestein filter: out[k] = DFT_L(b)[k] / L in long double, b the
 // conjugate chirp wrapped to length L.

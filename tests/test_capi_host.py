@@ -90,3 +90,29 @@ def test_plan_check_rejects(lib):
     assert shtx.plan_check(31, "octahedral", 63)[0] == -4
     assert shtx.plan_check(-1, "octahedral", 64)[0] == -1
     assert shtx.plan_check(31, "full", 64, nlon_full=0)[0] == -1
+
+
+@pytest.mark.parametrize("prec,shapes", [("fp32", [(128, 128), (64, 128), (128, 64)]),
+                                         ("fp64", [(64, 64), (32, 64), (64, 32)]),
+                                         ("bf16x3", [(128, 128), (64, 128)])])
+def test_plan_check_every_tuning_shape(lib, prec, shapes):
+    """Every tile shape and FFT blocking the autotuner may pick passes the
+    library's launch-shape checks on the workloads (host dry run)."""
+    import paper_1908_06097_amd as shtx
+    import synth_inputs as si
+    for key in ("t255_o256", "t399_o400"):
+        w = si.WORKLOADS[key]
+        for t in shapes:
+            for cap in (6144, 3072, 2048):
+                rc, info = shtx.plan_check_shapes(w.trunc, w.grid, w.nlat, w.nfld, prec, t, t, cap, w.nlon_full)
+                assert rc == 0, (key, prec, t, cap, rc)
+                assert tuple(info.inv_tile) == t and tuple(info.dir_tile) == t and info.fft_cap == cap
+
+
+def test_plan_check_shapes_rejects(lib):
+    import paper_1908_06097_amd as shtx
+    assert shtx.plan_check_shapes(255, "octahedral", 512, 7, "fp32", (96, 128), (128, 128), 6144)[0] == -4
+    assert shtx.plan_check_shapes(255, "octahedral", 512, 7, "fp32", (64, 64), (128, 128), 6144)[0] == -4
+    assert shtx.plan_check_shapes(255, "octahedral", 512, 7, "fp64", (128, 128), (64, 64), 6144)[0] == -4
+    assert shtx.plan_check_shapes(255, "octahedral", 512, 7, "fp32", (128, 128), (128, 128), 0)[0] == -1
+    assert shtx.plan_check_shapes(255, "octahedral", 512, 7, "fp32", (128, 128), (128, 128), 6145)[0] == -1
