@@ -28,7 +28,7 @@ int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 // Radices the ring-FFT kernel implements directly (primes; 4 and 8 are
 // formed from the factors of 2).
-const int kPrimeRadices[] = {2, 3, 5, 7};
+const int kPrimeRadices[] = {2, 3, 5, 7, 11, 13};
 
 // Factor n over the direct prime radices; returns the unfactored remainder.
 int smooth_factor(int n, std::vector<int> &f)
@@ -101,7 +101,7 @@ static void dft_ld(std::complex<long double> *x, int n, int stride,
 {
     if (n == 1) return;
     int p = 2;
-    for (int q : {2, 3, 5, 7})
+    for (int q : {2, 3, 5, 7, 11, 13})
         if (n % q == 0) {
             p = q;
             break;
