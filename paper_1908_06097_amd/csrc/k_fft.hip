@@ -4,9 +4,10 @@
 // A real ring of n = 2h points goes through one complex DFT of length h
 // (even samples as real part, odd samples as imaginary part) with the usual
 // split/merge step around it.  The length-h DFT is a Stockham autosort
-// mixed-radix FFT (radices 16, 9, 8, 4, 2, 3, 5, 7, 11, 13) held in LDS, run in
-// place: each pass reads its butterflies into registers, synchronises, then
-// writes.  Lengths with a prime factor above 13 go through Bluestein's chirp
+// mixed-radix FFT (radices 16, 9, 8, 4, 2, 3 and the primes 5 to 19; 17 in
+// FP64) held in LDS, run in place: each pass reads its butterflies into
+// registers, synchronises, then writes.  Lengths with a larger prime factor
+// go through Bluestein's chirp
 // convolution at a length L = 2^a 3^b >= 2h - 1, with the filter spectrum
 // precomputed per ring length at plan time.  Only the kept wavenumbers
 // m <= M_j are read or written; they live in the Fourier workspace laid out
@@ -24,6 +25,7 @@
 #include <cstdio>
 #include <cstdlib>
 
+#include "fft_roots.h"
 #include "shtx_internal.h"
 
 namespace shtx {
@@ -113,48 +115,15 @@ struct FftArgs {
     int64_t npts;
 };
 
-// exp(-2 pi i t / R) for the odd prime radices 5, 7, 11 and 13 (t taken
-// mod R), as compile-time constants.
+// exp(-2 pi i t / R) for the odd prime radices (t taken mod R), as
+// compile-time constants.
 template <typename T, int R>
 __device__ constexpr C2<T> root(int t)
 {
-    constexpr double c5[3] = {1.0, 0.30901699437494742410229341718281905886, -0.80901699437494742410229341718281905886};
-    constexpr double s5[3] = {0.0, 0.95105651629515357211643933337938214341, 0.58778525229247312916870595463907276860};
-    constexpr double c7[4] = {1.0, 0.62348980185873353052500488400423981063, -0.22252093395631440428890256449679475947,
-                              -0.90096886790241912623610231950744505117};
-    constexpr double s7[4] = {0.0, 0.78183148246802980870844452667405775023, 0.97492791218182360701813168299393121723,
-                              0.43388373911755812047576833284835875461};
-    constexpr double c11[6] = {1.0,
-                               0.84125353283118116886181164891936771751,
-                               0.41541501300188642552927414922962320352,
-                               -0.14231483827328514044379266861636966879,
-                               -0.65486073394528506405692507246629355318,
-                               -0.95949297361449738989036805706632769906};
-    constexpr double s11[6] = {0.0,
-                               0.54064081745559758210763595431869169543,
-                               0.90963199535451837141171538307902846006,
-                               0.98982144188093273237609203777671878738,
-                               0.75574957435425828377403584397234442018,
-                               0.28173255684142969771141791534661689904};
-    constexpr double c13[7] = {1.0,
-                               0.88545602565320989590037552201509887861,
-                               0.56806474673115580251180755912751662453,
-                               0.12053668025532305334906768745254358227,
-                               -0.35460488704253562596963789260001847432,
-                               -0.74851074817110109863463059970135138385,
-                               -0.97094181742605202715698227629378922725};
-    constexpr double s13[7] = {0.0,
-                               0.46472317204376854565601533513310477756,
-                               0.82298386589365639457961742343938199066,
-                               0.99270887409805399280075164949252017934,
-                               0.93501624268541482343978459983783072905,
-                               0.66312265824079520237678549266676627952,
-                               0.23931566428755776714875372626021189520};
     t %= R;
     const int u = t <= R / 2 ? t : R - t;
-    const double c = R == 5 ? c5[u] : R == 7 ? c7[u] : R == 11 ? c11[u] : c13[u];
-    const double sn = R == 5 ? s5[u] : R == 7 ? s7[u] : R == 11 ? s11[u] : s13[u];
-    return C2<T>{T(c), T(t <= R / 2 ? -sn : sn)};
+    const double sn = PrimeRoots<R>::s[u];
+    return C2<T>{T(PrimeRoots<R>::c[u]), T(t <= R / 2 ? -sn : sn)};
 }
 
 // Forward radix-R DFT of v in registers.
@@ -424,6 +393,12 @@ __device__ inline void pass_dispatch(int buf_off, int lbufp, int nf, const PassD
     case 7: stockham_pass<T, 7, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
     case 11: stockham_pass<T, 11, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
     case 13: stockham_pass<T, 13, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 17: stockham_pass<T, 17, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 19:
+        // FP64 plans stop at radix 17 (a radix-19 butterfly in FP64 would not
+        // fit the registers); the host never plans a radix-19 pass for them
+        if constexpr (sizeof(T) == 4) stockham_pass<T, 19, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat);
+        break;
     case 9: stockham_pass<T, 9, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
     case 16: stockham_pass<T, 16, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
     default: stockham_pass<T, 8, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
@@ -684,7 +659,8 @@ bool check_fft(const Plan &p, int cap)
         for (int s = 0; s < d.nrad; ++s) {
             int R = (int)((d.radcode >> (5 * s)) & 31u);
             bool ok = R == 4 || R == 8;
-            for (int q : {2, 3, 5, 7, 9, 11, 13, 16}) ok = ok || R == q;
+            for (int q : {2, 3, 5, 7, 9, 11, 13, 16, 17}) ok = ok || R == q;
+            ok = ok || (R == 19 && sizeof(T) == 4);
             if (!ok) SHTX_FFT_FAIL;
             // the pass descriptor must describe exactly this pass
             const PassDesc &pd = p.passes[d.pass_off + s];

@@ -26,16 +26,17 @@ int ring_cutoff(int trunc, int nlon)
 
 int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
-// Radices the ring-FFT kernel implements directly (primes; 4 and 8 are
-// formed from the factors of 2).
-const int kPrimeRadices[] = {2, 3, 5, 7, 11, 13};
+// Radices the ring-FFT kernel implements directly (primes; 4, 8, 9 and 16
+// are formed from the factors of 2 and 3).  FP64 plans stop at 17.
+const int kPrimeRadices[] = {2, 3, 5, 7, 11, 13, 17, 19};
 
-// Factor n over the direct prime radices; returns the unfactored remainder.
-int smooth_factor(int n, std::vector<int> &f)
+// Factor n over the direct prime radices up to maxp; returns the unfactored
+// remainder.
+int smooth_factor(int n, std::vector<int> &f, int maxp = 19)
 {
     f.clear();
     for (int p : kPrimeRadices)
-        while (n % p == 0) {
+        while (p <= maxp && n % p == 0) {
             f.push_back(p);
             n /= p;
         }
@@ -93,7 +94,7 @@ void gemm_tiles(int prec, int *inv_bm, int *inv_bn, int *dir_bm, int *dir_bn)
     }
 }
 
-// Long-double mixed-radix DFT (forward) over a 7-smooth length, used once per
+// Long-double mixed-radix DFT (forward) over a 2^a 3^b length, used once per
 // ring length at plan time for the Bluestein filter spectrum.
 static void dft_ld(std::complex<long double> *x, int n, int stride,
                    const std::vector<std::complex<long double>> &tw, int N,
@@ -101,7 +102,7 @@ static void dft_ld(std::complex<long double> *x, int n, int stride,
 {
     if (n == 1) return;
     int p = 2;
-    for (int q : {2, 3, 5, 7, 11, 13})
+    for (int q : {2, 3, 5, 7, 11, 13, 17, 19})
         if (n % q == 0) {
             p = q;
             break;
@@ -318,7 +319,7 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         int h = n / 2;
         LenPlan lp{};
         std::vector<int> f;
-        if (smooth_factor(h, f) == 1) {
+        if (smooth_factor(h, f, dbl ? 17 : 19) == 1) {
             lp.L = h;
             lp.blue = 0;
         } else {
