@@ -250,6 +250,12 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
     store(0);
     if (!INV && nstages > 1) meta(BK, mp1, mq1);
     __syncthreads();
+    // a wave whose whole sub-tile lies past the valid rows or columns (the
+    // ragged edge of an m block or of the field range) still loads and
+    // stores its share of the operand tiles but skips the MFMAs, leaving its
+    // SIMD to the other resident block
+    const bool mfma_on = __builtin_amdgcn_readfirstlane(
+        (row0 + wr < (INV ? b.R : b.K0) && col0 + wc < ncol) ? 1 : 0);
     for (int s = 0; s < nstages; ++s) {
         const int cur = s & 1;
         const bool more = s + 1 < nstages;
@@ -257,6 +263,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
         if (!INV && s + 2 < nstages) meta((s + 2) * BK, mp2, mq2);
 #pragma unroll
         for (int q = 0; q < BK; q += 4) {
+            if (!mfma_on) break;
             const int qq = q + (lane >> 4);
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
