@@ -4,7 +4,7 @@
 // A real ring of n = 2h points goes through one complex DFT of length h
 // (even samples as real part, odd samples as imaginary part) with the usual
 // split/merge step around it.  The length-h DFT is a Stockham autosort
-// mixed-radix FFT (radices 16, 9, 8, 4, 2, 3 and the primes 5 to 19; 17 in
+// mixed-radix FFT (radices 16, 9, 8, 4, 2, 3 and the primes 5 to 23; 17 in
 // FP64) held in LDS, run in place: each pass reads its butterflies into
 // registers, synchronises, then writes.  Lengths with a larger prime factor
 // go through Bluestein's chirp
@@ -293,6 +293,40 @@ __device__ inline void twiddle_powers(C2<T> *tw, C2<T> w1, C2<T> w2nd)
     }
 }
 
+// Radix-R DFT (R odd prime) of v, written to LDS as it is formed: output t
+// goes to byte address a0 + t * stride.  Sums and differences of the pairs
+// (r, R - r) replace the inputs in place, so only the inputs and two
+// accumulators are live (the same arithmetic as dft_reg's odd radices).
+template <typename T, int R>
+__device__ inline void odd_butterfly_store(C2<T> *v, unsigned a0, unsigned stride)
+{
+    constexpr int H = (R - 1) / 2;
+    const C2<T> x0 = v[0];
+    C2<T> out0 = x0;
+#pragma unroll
+    for (int r = 1; r <= H; ++r) {
+        const C2<T> sm = cadd(v[r], v[R - r]), df = csub(v[r], v[R - r]);
+        v[r] = sm;
+        v[R - r] = df;
+        out0 = cadd(out0, sm);
+    }
+    stb<T>(a0, out0);
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        C2<T> re = x0, im = {T(0), T(0)};
+#pragma unroll
+        for (int r = 1; r <= H; ++r) {
+            const C2<T> w = root<T, R>(k * r);  // (cos, -sin) of 2 pi k r / R
+            re.x += v[r].x * w.x;
+            re.y += v[r].y * w.x;
+            im.x += v[R - r].x * w.y;
+            im.y += v[R - r].y * w.y;
+        }
+        stb<T>(a0 + __umul24((unsigned)k, stride), C2<T>{re.x - im.y, re.y + im.x});
+        stb<T>(a0 + __umul24((unsigned)(R - k), stride), C2<T>{re.x + im.y, re.y - im.x});
+    }
+}
+
 // One in-place Stockham pass of radix R over nf fields of length L in LDS:
 // every thread reads all of its butterflies into registers, the block
 // synchronises, then each butterfly is twiddled, transformed and written.
@@ -306,13 +340,18 @@ template <typename T, int R, int CAP, bool BHAT, typename WPtr>
 __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lbufp, int nf, PassDesc pd, WPtr W,
                                                              GlobalC2<T> *bhat)
 {
-    constexpr int NB = (CAP / R + kFftThreads - 1) / kFftThreads;
+    constexpr int NB = fft_rounds(CAP, R);
     constexpr int C2ND = twiddle_step2<R>();
     constexpr unsigned CB = sizeof(C2<T>);
     const int nbf = pd.nbf, total = nf * nbf, Ns = pd.Ns;
     const unsigned srd = nbf * CB, swr = Ns * CB;  // byte strides of a butterfly's reads and writes
+    // radices above 19 run a streamed butterfly: twiddles by stepping from
+    // table values read every 8 powers, outputs stored as they are formed
+    constexpr bool STREAM = R > 19;
+    constexpr int NRS = STREAM ? (R + 6) / 8 : 1;  // table restarts at powers 1, 9, 17, 25
     C2<T> v[NB][R];
     C2<T> w1[NB], w2[NB];  // twiddle table values, fetched before the barrier
+    C2<T> wrs[NB][NRS];
     int fo[NB], qk[NB][2];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -327,6 +366,10 @@ __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lb
                 const int t1 = k * pd.tstep;
                 w1[b] = C2<T>{W[t1].x, W[t1].y};
                 if constexpr (C2ND > 0) w2[b] = C2<T>{W[C2ND * t1].x, W[C2ND * t1].y};
+                if constexpr (STREAM) {
+#pragma unroll
+                    for (int c = 0; c < NRS; ++c) wrs[b][c] = C2<T>{W[(8 * c + 1) * t1].x, W[(8 * c + 1) * t1].y};
+                }
             }
             const unsigned a0 = (unsigned)(fo[b] + j) * CB;
 #pragma unroll
@@ -347,16 +390,28 @@ __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lb
         if (e < total) {
             const int q = qk[b][0], k = qk[b][1];
             const int base = q * Ns * R + k;
-            if (Ns > 1) {
-                C2<T> tw[R];
-                twiddle_powers<T, R>(tw, w1[b], w2[b]);
-#pragma unroll
-                for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r]);
-            }
-            dft_reg<T, R>(v[b]);
             const unsigned a0 = (unsigned)(fo[b] + base) * CB;
+            if constexpr (STREAM) {
+                if (Ns > 1) {
+                    C2<T> t = wrs[b][0];
 #pragma unroll
-            for (int r = 0; r < R; ++r) stb<T>(a0 + __umul24((unsigned)r, swr), v[b][r]);
+                    for (int r = 1; r < R; ++r) {
+                        if (r > 1) t = ((r - 1) % 8 == 0) ? wrs[b][(r - 1) / 8] : cmul(t, w1[b]);
+                        v[b][r] = cmul(v[b][r], t);
+                    }
+                }
+                odd_butterfly_store<T, R>(v[b], a0, swr);
+            } else {
+                if (Ns > 1) {
+                    C2<T> tw[R];
+                    twiddle_powers<T, R>(tw, w1[b], w2[b]);
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[b][r] = cmul(v[b][r], tw[r]);
+                }
+                dft_reg<T, R>(v[b]);
+#pragma unroll
+                for (int r = 0; r < R; ++r) stb<T>(a0 + __umul24((unsigned)r, swr), v[b][r]);
+            }
         }
     }
     __syncthreads();
@@ -394,11 +449,15 @@ __device__ inline void pass_dispatch(int buf_off, int lbufp, int nf, const PassD
     case 11: stockham_pass<T, 11, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
     case 13: stockham_pass<T, 13, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
     case 17: stockham_pass<T, 17, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    // FP64 plans stop at radix 17 (larger FP64 butterflies would not fit the
+    // registers); the host never plans the radices below for them
     case 19:
-        // FP64 plans stop at radix 17 (a radix-19 butterfly in FP64 would not
-        // fit the registers); the host never plans a radix-19 pass for them
         if constexpr (sizeof(T) == 4) stockham_pass<T, 19, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat);
         break;
+    case 23:
+        if constexpr (sizeof(T) == 4) stockham_pass<T, 23, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat);
+        break;
+
     case 9: stockham_pass<T, 9, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
     case 16: stockham_pass<T, 16, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
     default: stockham_pass<T, 8, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
@@ -658,9 +717,11 @@ bool check_fft(const Plan &p, int cap)
         int prod = 1;
         for (int s = 0; s < d.nrad; ++s) {
             int R = (int)((d.radcode >> (5 * s)) & 31u);
+            // every butterfly of a block's fields is covered by the pass's rounds
+            if (R > 0 && (int64_t)d.fb * (d.L / R) > (int64_t)fft_rounds(cap, R) * kFftThreads) SHTX_FFT_FAIL;
             bool ok = R == 4 || R == 8;
             for (int q : {2, 3, 5, 7, 9, 11, 13, 16, 17}) ok = ok || R == q;
-            ok = ok || (R == 19 && sizeof(T) == 4);
+            ok = ok || ((R == 19 || R == 23) && sizeof(T) == 4);
             if (!ok) SHTX_FFT_FAIL;
             // the pass descriptor must describe exactly this pass
             const PassDesc &pd = p.passes[d.pass_off + s];

@@ -147,6 +147,8 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
 #pragma unroll
         for (int v = 0; v < NM; ++v) {
             int r = kk + (tid + v * 256) / (BN / 2);
+            // with 64 fields per tile a wave's ring is uniform: scalar loads
+            if constexpr (BN / 2 == 64) r = __builtin_amdgcn_readfirstlane(r);
             RingPair o = {-1, -1};
             T w = T(0);
             if (r < b.R) {

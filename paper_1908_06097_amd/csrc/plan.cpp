@@ -28,11 +28,11 @@ int64_t round_up(int64_t x, int64_t q) { return (x + q - 1) / q * q; }
 
 // Radices the ring-FFT kernel implements directly (primes; 4, 8, 9 and 16
 // are formed from the factors of 2 and 3).  FP64 plans stop at 17.
-const int kPrimeRadices[] = {2, 3, 5, 7, 11, 13, 17, 19};
+const int kPrimeRadices[] = {2, 3, 5, 7, 11, 13, 17, 19, 23};
 
 // Factor n over the direct prime radices up to maxp; returns the unfactored
 // remainder.
-int smooth_factor(int n, std::vector<int> &f, int maxp = 19)
+int smooth_factor(int n, std::vector<int> &f, int maxp = 23)
 {
     f.clear();
     for (int p : kPrimeRadices)
@@ -102,7 +102,7 @@ static void dft_ld(std::complex<long double> *x, int n, int stride,
 {
     if (n == 1) return;
     int p = 2;
-    for (int q : {2, 3, 5, 7, 11, 13, 17, 19})
+    for (int q : {2, 3, 5, 7, 11, 13, 17, 19, 23})
         if (n % q == 0) {
             p = q;
             break;
@@ -184,6 +184,13 @@ int fft_blocking(Plan &p, int cap)
         RingDesc &d = p.rings[j];
         if (d.lbuf > maxcap) return SHTX_EUNSUPPORTED;
         d.fb = std::max(1, std::min(F, cap / d.lbuf));
+        // passes of radix 11 and up run one round of kFftThreads butterflies
+        for (int s = 0; s < d.nrad; ++s) {
+            const int R = (int)((d.radcode >> (5 * s)) & 31u);
+            const int lim = fft_rounds(maxcap, R) * kFftThreads / (d.L / R);
+            if (lim < 1) return SHTX_EUNSUPPORTED;
+            d.fb = std::min(d.fb, lim);
+        }
         lds_elems = std::max(lds_elems, d.fb * d.lbufp);
         lds_tw = std::max(lds_tw, d.fb * d.lbufp + d.L);
         std::vector<FftItem> g;
@@ -319,7 +326,7 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         int h = n / 2;
         LenPlan lp{};
         std::vector<int> f;
-        if (smooth_factor(h, f, dbl ? 17 : 19) == 1) {
+        if (smooth_factor(h, f, dbl ? 17 : 23) == 1) {
             lp.L = h;
             lp.blue = 0;
         } else {

@@ -20,6 +20,15 @@ constexpr int kTablePad = 128;
 constexpr int kFftCapF32 = 6144;  // 48 KiB before padding
 constexpr int kFftCapF64 = 6144;  // 96 KiB
 constexpr int kFftThreads = 512;
+
+// Butterflies per thread in a radix-R Stockham pass (rounds of kFftThreads):
+// enough for a block's cap complex values for radices below 11; radices 11
+// and up take one round, and the blocking keeps a block's fields within it
+// (they only occur in rings whose whole FFT is a direct one).
+__host__ __device__ constexpr int fft_rounds(int cap, int R)
+{
+    return R >= 11 ? 1 : (cap / R + kFftThreads - 1) / kFftThreads;
+}
 constexpr int kMaxRadices = 12;
 
 // One m block of the Legendre tables.
