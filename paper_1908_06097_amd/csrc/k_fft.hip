@@ -6,8 +6,9 @@
 // split/merge step around it.  The length-h DFT is a Stockham autosort
 // mixed-radix FFT (radices 16, 9, 8, 4, 2, 3 and the primes 5 to 23; 17 in
 // FP64) held in LDS, run in place: each pass reads its butterflies into
-// registers, synchronises, then writes.  Lengths with a larger prime factor
-// go through Bluestein's chirp
+// registers, synchronises, then writes.  One larger prime factor up to 127
+// runs as a general prime pass (below); other lengths go through Bluestein's
+// chirp
 // convolution at a length L = 2^a 3^b >= 2h - 1, with the filter spectrum
 // precomputed per ring length at plan time.  Only the kept wavenumbers
 // m <= M_j are read or written; they live in the Fourier workspace laid out
@@ -430,6 +431,108 @@ __device__ inline void stockham_pass(int buf_off, int lbufp, int nf, const PassD
         stockham_pass_impl<T, R, CAP, BHAT>(buf_off, lbufp, nf, pd, (GlobalC2<T> *)Wg, (GlobalC2<T> *)bhat);
 }
 
+// Radices above the register butterflies run as the general prime pass.
+template <typename T>
+__host__ __device__ constexpr bool is_gp_radix(int R)
+{
+    return R > (sizeof(T) == 4 ? 23 : 17);
+}
+
+// General prime pass (radix p = pd.R, an odd prime, first pass so Ns = 1 and
+// no input twiddles).  With x_r the inputs of a butterfly,
+//   X_0 = x_0 + sum_r s_r,
+//   X_t, X_{p-t} = x_0 + sum_r (s_r cos(2 pi r t / p) -+ i d_r sin(2 pi r t / p)),
+// s_r = x_r + x_{p-r}, d_r = x_r - x_{p-r}, r = 1 .. (p-1)/2.  The pairs
+// (s_r, d_r) replace the inputs in LDS; each work item then forms the outputs
+// of one butterfly for a block of 4 consecutive t, stepping the roots by
+// e^{-2 pi i r / p} from a table of the p-th roots held in LDS, keeps them in
+// registers over a barrier (the pass is in place) and writes them.
+template <typename T, typename WPtr>
+__device__ __attribute__((noinline)) void gp_pass(int buf_off, int lbufp, int nf, PassDesc pd, WPtr W)
+{
+    constexpr unsigned CB = sizeof(C2<T>);
+    const int p = pd.R, H = (p - 1) / 2, nbf = pd.nbf, TB = gp_tblocks(p);
+    const int roots_off = buf_off + nf * lbufp;
+    // 1. e^{-2 pi i u / p} = W_L[u nbf]
+    for (int u = threadIdx.x; u < p; u += kFftThreads) stb<T>((unsigned)(roots_off + u) * CB, C2<T>{W[u * nbf].x, W[u * nbf].y});
+    // 2. slot r <- s_r, slot p - r <- d_r (each item owns one pair)
+    const int hn = H * nbf, na = nf * hn;
+    const unsigned mg_hn = div_magic(hn);
+    for (int e = threadIdx.x; e < na; e += kFftThreads) {
+        const int f = udiv(e, mg_hn), rem = e - f * hn;
+        const int r1 = udiv(rem, pd.mg_nbf), j = rem - r1 * nbf;
+        const int sl = buf_off + f * lbufp + j;
+        const unsigned ar = (unsigned)(sl + (r1 + 1) * nbf) * CB, ap = (unsigned)(sl + (p - 1 - r1) * nbf) * CB;
+        const C2<T> x = ldb<T>(ar), y = ldb<T>(ap);
+        stb<T>(ar, cadd(x, y));
+        stb<T>(ap, csub(x, y));
+    }
+    __syncthreads();
+    // 3. outputs of each (field, butterfly, block of 4 t) item into registers
+    const int jt = nbf * TB, nb = nf * jt;
+    const unsigned mg_jt = div_magic(jt), mg_tb = div_magic(TB);
+    C2<T> out[kGpRounds][9];
+    int obase[kGpRounds], ot0[kGpRounds];
+#pragma unroll
+    for (int g = 0; g < kGpRounds; ++g) {
+        const int e = threadIdx.x + g * kFftThreads;
+        ot0[g] = -1;
+        if (e < nb) {
+            const int f = udiv(e, mg_jt), rem = e - f * jt;
+            const int j = udiv(rem, mg_tb), tb = rem - j * TB;
+            const int t0 = 1 + 4 * tb;
+            const int sl = buf_off + f * lbufp + j;
+            const C2<T> x0 = ldb<T>((unsigned)sl * CB);
+            C2<T> sum = x0, re[4] = {x0, x0, x0, x0}, im[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) im[q] = C2<T>{T(0), T(0)};
+            int u = 0;  // r t0 mod p
+            for (int r = 1; r <= H; ++r) {
+                u += t0;
+                if (u >= p) u -= p;
+                const C2<T> sr = ldb<T>((unsigned)(sl + r * nbf) * CB);
+                const C2<T> dr = ldb<T>((unsigned)(sl + (p - r) * nbf) * CB);
+                const C2<T> st = ldb<T>((unsigned)(roots_off + r) * CB);
+                C2<T> w = ldb<T>((unsigned)(roots_off + u) * CB);
+                sum = cadd(sum, sr);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (q > 0) w = cmul(w, st);  // e^{-2 pi i r (t0 + q) / p}
+                    re[q].x += sr.x * w.x;
+                    re[q].y += sr.y * w.x;
+                    im[q].x += dr.x * w.y;
+                    im[q].y += dr.y * w.y;
+                }
+            }
+            out[g][0] = sum;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                out[g][1 + 2 * q] = C2<T>{re[q].x - im[q].y, re[q].y + im[q].x};  // X_{t0+q}
+                out[g][2 + 2 * q] = C2<T>{re[q].x + im[q].y, re[q].y - im[q].x};  // X_{p-t0-q}
+            }
+            obase[g] = buf_off + f * lbufp + j * p;
+            ot0[g] = t0;
+        }
+    }
+    __syncthreads();
+    // 4. X_t of butterfly j goes to j p + t (Stockham output order at Ns = 1)
+#pragma unroll
+    for (int g = 0; g < kGpRounds; ++g) {
+        const int t0 = ot0[g];
+        if (t0 < 0) continue;
+        const int ob = obase[g];
+        if (t0 == 1) stb<T>((unsigned)ob * CB, out[g][0]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int t = t0 + q;
+            if (t > H) break;
+            stb<T>((unsigned)(ob + t) * CB, out[g][1 + 2 * q]);
+            stb<T>((unsigned)(ob + p - t) * CB, out[g][2 + 2 * q]);
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T, int CAP, bool TWL, bool BHAT>
 __device__ inline void pass_dispatch(int buf_off, int lbufp, int nf, const PassDesc &pd, const C2<T> *W,
                                      const C2<T> *bhat)
@@ -438,6 +541,13 @@ __device__ inline void pass_dispatch(int buf_off, int lbufp, int nf, const PassD
         // Bluestein lengths are 2^a 3^b with 9 | L and the radix-9 passes first
         // (checked on the host), so the filter pass is always radix 9
         stockham_pass<T, 9, CAP, TWL, true>(buf_off, lbufp, nf, pd, W, bhat);
+        return;
+    }
+    if (is_gp_radix<T>(pd.R)) {
+        if constexpr (TWL)
+            gp_pass<T>(buf_off, lbufp, nf, pd, (const LdsC2<T> *)lds_c2<T>());
+        else
+            gp_pass<T>(buf_off, lbufp, nf, pd, (GlobalC2<T> *)W);
         return;
     }
     switch (pd.R) {
@@ -703,7 +813,6 @@ bool check_fft(const Plan &p, int cap)
     for (const RingDesc &d : p.rings) {
         if (d.lbuf > cap || d.L > d.lbuf || d.h + 1 > d.lbuf || d.M >= d.h) SHTX_FFT_FAIL;
         if (d.lbufp < d.lbuf) SHTX_FFT_FAIL;
-        if ((size_t)(d.fb * d.lbufp + (p.fft_tw_lds ? d.L : 0)) * celem > (size_t)p.fft_lds_bytes) SHTX_FFT_FAIL;
         if (d.tw_off < 0 || d.tw_off + d.L > p.twid_elems) SHTX_FFT_FAIL;
         if (d.post_off < 0 || d.post_off + d.h + 1 > p.twid_elems) SHTX_FFT_FAIL;
         if (d.blue && (d.chirp_off < 0 || d.chirp_off + d.h > p.twid_elems || d.bhat_off < 0 ||
@@ -711,26 +820,42 @@ bool check_fft(const Plan &p, int cap)
             SHTX_FFT_FAIL;
         if (d.grid_off + d.n > p.npts || d.four_off + (int64_t)(d.M + 1) * p.nfld > p.nfour * p.nfld)
             SHTX_FFT_FAIL;
-        if (d.pass_off < 0 || d.pass_off + d.nrad > (int)p.passes.size()) SHTX_FFT_FAIL;
+        if (d.pass_off < 0 || d.pass_off + d.nrad > (int)p.passes.size() || d.nrad < 1) SHTX_FFT_FAIL;
         // the second Bluestein FFT applies the filter in a radix-9 first pass
-        if (d.blue && (d.nrad < 1 || (d.radcode & 31u) != 9u)) SHTX_FFT_FAIL;
-        int prod = 1;
+        if (d.blue && p.passes[d.pass_off].R != 9) SHTX_FFT_FAIL;
+        int prod = 1, extra = 0;
         for (int s = 0; s < d.nrad; ++s) {
-            int R = (int)((d.radcode >> (5 * s)) & 31u);
-            // every butterfly of a block's fields is covered by the pass's rounds
-            if (R > 0 && (int64_t)d.fb * (d.L / R) > (int64_t)fft_rounds(cap, R) * kFftThreads) SHTX_FFT_FAIL;
-            bool ok = R == 4 || R == 8;
-            for (int q : {2, 3, 5, 7, 9, 11, 13, 16, 17}) ok = ok || R == q;
-            ok = ok || ((R == 19 || R == 23) && sizeof(T) == 4);
-            if (!ok) SHTX_FFT_FAIL;
-            // the pass descriptor must describe exactly this pass
             const PassDesc &pd = p.passes[d.pass_off + s];
-            if (pd.R != R || pd.Ns != prod || pd.nbf * R != d.L || pd.tstep * prod * R != d.L) SHTX_FFT_FAIL;
+            const int R = pd.R;
+            const int code = (int)((d.radcode >> (5 * s)) & 31u);
+            if (R < 2 || d.L % R) SHTX_FFT_FAIL;
+            if (is_gp_radix<T>(R)) {
+                // a general prime pass: the first pass only, an odd prime up to
+                // kGpMaxPrime, its results held for kGpRounds items per thread
+                if (s != 0 || code != 0 || R > kGpMaxPrime || R % 2 == 0 || d.blue) SHTX_FFT_FAIL;
+                for (int q = 3; q * q <= R; q += 2)
+                    if (R % q == 0) SHTX_FFT_FAIL;
+                if ((int64_t)d.fb * pd.nbf * gp_tblocks(R) > (int64_t)kGpRounds * kFftThreads) SHTX_FFT_FAIL;
+                extra = kGpRootSlots;
+            } else {
+                bool ok = R == 4 || R == 8;
+                for (int q : {2, 3, 5, 7, 9, 11, 13, 16, 17}) ok = ok || R == q;
+                ok = ok || ((R == 19 || R == 23) && sizeof(T) == 4);
+                if (!ok || code != R) SHTX_FFT_FAIL;
+                // every butterfly of a block's fields is covered by the pass's rounds
+                if ((int64_t)d.fb * (d.L / R) > (int64_t)fft_rounds(cap, R) * kFftThreads) SHTX_FFT_FAIL;
+            }
+            // the pass descriptor must describe exactly this pass
+            if (pd.Ns != prod || pd.nbf * R != d.L || pd.tstep * prod * R != d.L) SHTX_FFT_FAIL;
             if (pd.mg_nbf != div_magic(pd.nbf) || pd.mg_ns != div_magic(pd.Ns)) SHTX_FFT_FAIL;
-            // twiddle reads W[c k tstep] (c = 1, and 3 or 4 for radix 9 or 16), k < Ns
-            if (prod > 1 && (int64_t)(R == 16 ? 4 : R == 9 ? 3 : 1) * (prod - 1) * pd.tstep >= d.L) SHTX_FFT_FAIL;
+            // twiddle reads W[c k tstep] (c = 1, and 3 or 4 for radix 9 or 16;
+            // 1, 9, 17 for the streamed radix 23), k < Ns
+            const int cmax = R == 16 ? 4 : R == 9 ? 3 : R > 19 ? 17 : 1;
+            if (prod > 1 && (int64_t)cmax * (prod - 1) * pd.tstep >= d.L) SHTX_FFT_FAIL;
             prod *= R;
         }
+        if ((size_t)(d.fb * d.lbufp + extra + (p.fft_tw_lds ? d.L : 0)) * celem > (size_t)p.fft_lds_bytes)
+            SHTX_FFT_FAIL;
         if (prod != d.L) SHTX_FFT_FAIL;
     }
     for (const FftItem &it : p.fft_items) {

@@ -43,6 +43,14 @@ int smooth_factor(int n, std::vector<int> &f, int maxp = 23)
     return n;
 }
 
+bool is_prime(int n)
+{
+    if (n < 2) return false;
+    for (int q = 2; q * q <= n; ++q)
+        if (n % q == 0) return false;
+    return true;
+}
+
 // Stockham radices for a smooth length: the odd factors first, largest
 // first (the first pass needs no twiddles), with pairs of 3 merged into 9;
 // then the power of two as radix-16 passes and one 8, 4 or 2.
@@ -184,15 +192,25 @@ int fft_blocking(Plan &p, int cap)
         RingDesc &d = p.rings[j];
         if (d.lbuf > maxcap) return SHTX_EUNSUPPORTED;
         d.fb = std::max(1, std::min(F, cap / d.lbuf));
-        // passes of radix 11 and up run one round of kFftThreads butterflies
+        // passes of radix 11 and up run one round of kFftThreads butterflies;
+        // a general prime pass keeps its outputs for kGpRounds rounds of
+        // (butterfly, block of 4 output pairs) items
+        int extra = 0;
         for (int s = 0; s < d.nrad; ++s) {
-            const int R = (int)((d.radcode >> (5 * s)) & 31u);
-            const int lim = fft_rounds(maxcap, R) * kFftThreads / (d.L / R);
+            const PassDesc &q = p.passes[d.pass_off + s];
+            const int R = q.R;
+            int lim;
+            if (R > 23 || (p.prec == SHTX_FP64 && R > 17)) {
+                lim = kGpRounds * kFftThreads / (q.nbf * gp_tblocks(R));
+                extra = kGpRootSlots;
+            } else {
+                lim = fft_rounds(maxcap, R) * kFftThreads / q.nbf;
+            }
             if (lim < 1) return SHTX_EUNSUPPORTED;
             d.fb = std::min(d.fb, lim);
         }
-        lds_elems = std::max(lds_elems, d.fb * d.lbufp);
-        lds_tw = std::max(lds_tw, d.fb * d.lbufp + d.L);
+        lds_elems = std::max(lds_elems, d.fb * d.lbufp + extra);
+        lds_tw = std::max(lds_tw, d.fb * d.lbufp + extra + d.L);
         std::vector<FftItem> g;
         for (int f0 = 0; f0 < F; f0 += d.fb) g.push_back(FftItem{j, f0, std::min(d.fb, F - f0), 0});
         fgroups.push_back(g);
@@ -326,7 +344,12 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         int h = n / 2;
         LenPlan lp{};
         std::vector<int> f;
-        if (smooth_factor(h, f, dbl ? 17 : 23) == 1) {
+        const int maxp = dbl ? 17 : 23;
+        const int rem = smooth_factor(h, f, maxp);
+        // one prime factor above the register radices, up to kGpMaxPrime, is
+        // run as a general prime pass (first, at Ns = 1) instead of Bluestein
+        const bool gp = rem > 1 && rem <= kGpMaxPrime && is_prime(rem);
+        if (rem == 1 || gp) {
             lp.L = h;
             lp.blue = 0;
         } else {
@@ -345,7 +368,12 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
             lp.blue = 1;
         }
         if (std::max(lp.L, h + 1) > cap) return SHTX_EUNSUPPORTED;
-        lp.rad = radices_for(lp.L);
+        if (gp) {
+            lp.rad = radices_for(lp.L / rem);
+            lp.rad.insert(lp.rad.begin(), rem);
+        } else {
+            lp.rad = radices_for(lp.L);
+        }
         if ((int)lp.rad.size() > kMaxRadices) return SHTX_EUNSUPPORTED;
         lp.pass_off = (int)p.passes.size();
         for (int s = 0, Ns = 1; s < (int)lp.rad.size(); Ns *= lp.rad[s], ++s) {
@@ -405,7 +433,11 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         d.nrad = (int)lp.rad.size();
         d.pass_off = lp.pass_off;
         d.radcode = 0;
-        for (int r = 0; r < d.nrad; ++r) d.radcode |= (unsigned long long)lp.rad[r] << (5 * r);
+        // code 0 marks a general prime pass (its radix is in the pass descriptor)
+        for (int r = 0; r < d.nrad; ++r) {
+            const bool gp = lp.rad[r] > (prec == SHTX_FP64 ? 17 : 23);
+            d.radcode |= (unsigned long long)(gp ? 0 : lp.rad[r]) << (5 * r);
+        }
         d.lbuf = std::max(d.L, d.h + 1);
         d.lbufp = d.lbuf;
         d.tw_off = lp.tw;

@@ -29,6 +29,16 @@ __host__ __device__ constexpr int fft_rounds(int cap, int R)
 {
     return R >= 11 ? 1 : (cap / R + kFftThreads - 1) / kFftThreads;
 }
+
+// General prime pass: a ring whose half-length has one prime factor p above
+// the register radices, p <= kGpMaxPrime, runs it as the first pass with the
+// p-th roots of unity in kGpRootSlots LDS entries after the field slots.  Each
+// work item is one butterfly and a block of 4 output pairs; a block holds its
+// results for at most kGpRounds items per thread.
+constexpr int kGpMaxPrime = 127;
+constexpr int kGpRootSlots = 128;
+constexpr int kGpRounds = 2;
+__host__ __device__ constexpr int gp_tblocks(int p) { return ((p - 1) / 2 + 3) / 4; }
 constexpr int kMaxRadices = 12;
 
 // One m block of the Legendre tables.
