@@ -6,7 +6,7 @@
 // split/merge step around it.  The length-h DFT is a Stockham autosort
 // mixed-radix FFT (radices 16, 9, 8, 4, 2, 3 and the primes 5 to 23; 17 in
 // FP64) held in LDS, run in place: each pass reads its butterflies into
-// registers, synchronises, then writes.  One larger prime factor up to 127
+// registers, synchronises, then writes.  One larger prime factor up to 191
 // runs as a general prime pass (below); other lengths go through Bluestein's
 // chirp
 // convolution at a length L = 2^a 3^b >= 2h - 1, with the filter spectrum

@@ -35,8 +35,8 @@ __host__ __device__ constexpr int fft_rounds(int cap, int R)
 // p-th roots of unity in kGpRootSlots LDS entries after the field slots.  Each
 // work item is one butterfly and a block of 4 output pairs; a block holds its
 // results for at most kGpRounds items per thread.
-constexpr int kGpMaxPrime = 127;
-constexpr int kGpRootSlots = 128;
+constexpr int kGpMaxPrime = 191;
+constexpr int kGpRootSlots = 192;
 constexpr int kGpRounds = 2;
 __host__ __device__ constexpr int gp_tblocks(int p) { return ((p - 1) / 2 + 3) / 4; }
 constexpr int kMaxRadices = 12;
