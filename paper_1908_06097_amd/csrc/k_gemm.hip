@@ -112,8 +112,12 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
     static_assert(BK == 16 && BN >= 32, "operand swizzle assumes 16-deep stages");
     typedef typename Acc<T>::type V;
     typedef T VecT __attribute__((ext_vector_type(VEC)));
-    __shared__ __attribute__((aligned(16))) T As[2][2][BK][LDA];
-    __shared__ __attribute__((aligned(16))) T Bs[2][2][BK][LDB];
+    // operand tiles As[buf][p][kappa][i], Bs[buf][p][kappa][j]; the direct
+    // GEMM reuses the same LDS to stage its output tile
+    constexpr int NSMEM = 2 * 2 * BK * (LDA + LDB);
+    __shared__ __attribute__((aligned(16))) T smem[NSMEM];
+    auto As = reinterpret_cast<T(*)[2][BK][LDA]>(smem);
+    auto Bs = reinterpret_cast<T(*)[2][BK][LDB]>(smem + 2 * 2 * BK * LDA);
 
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const GemmItem it = a.items[item];
@@ -321,7 +325,9 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
                     }
                 }
             }
-    } else {
+    } else if constexpr (sizeof(T) == 8) {
+        // FP64: direct scattered stores (staging measured slower for the
+        // smaller FP64 tiles)
         T *spec = (T *)a.out;
 #pragma unroll
         for (int p = 0; p < 2; ++p)
@@ -340,6 +346,45 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
                             spec[2 * ((int64_t)(c >> 1) * a.nspec + sb + nrel) + (c & 1)] = val;
                         }
                     }
+    } else {
+        // The tile covers n = m + 2 row0 + (0 .. 2 BM - 1) for BN/2 fields: each
+        // column half (the fields of waves with the same wc) is staged in LDS
+        // as [field][n] and written as contiguous runs of one field's spectrum.
+        constexpr int FH = BN / 4;      // fields per column half
+        constexpr int RS = 2 * BM + 1;  // staged complex values per field, padded
+        static_assert(FH * RS * 2 <= NSMEM, "staged output half must fit the operand LDS");
+        Vec2<T> *spec = (Vec2<T> *)a.out;
+        const int nrel0 = 2 * row0;
+        const int nvalid = min(2 * BM, a.trunc - m - nrel0 + 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            __syncthreads();  // the K loop's (or the previous half's) LDS reads are done
+            if ((wave & 1) == h) {
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int k = wr + i * 16 + acc_row<T>(lane, v);
+                                const int cl = j * 16 + (lane & 15);
+                                T val = acc[p][i][j][v];
+                                if (m == 0 && (cl & 1)) val = 0;
+                                smem[((cl >> 1) * RS + p + 2 * k) * 2 + (cl & 1)] = val;
+                            }
+            }
+            __syncthreads();
+            const int fbase = col0 / 2 + h * FH;
+            for (int fl = wave; fl < FH; fl += 4) {
+                const int f = fbase + fl;
+                if (f >= a.nfld) break;
+                Vec2<T> *dst = spec + (int64_t)f * a.nspec + sb + nrel0;
+                for (int nr = lane; nr < nvalid; nr += 64)
+                    dst[nr] = Vec2<T>{smem[(fl * RS + nr) * 2], smem[(fl * RS + nr) * 2 + 1]};
+            }
+        }
     }
 }
 
