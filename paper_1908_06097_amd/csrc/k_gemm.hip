@@ -421,8 +421,12 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
     constexpr int NU = INVERSE ? (BN / 2) * 2 * (BK / 8) / 256 : (BN / 2) * (BK / 8) / 256;
     static_assert(NA * 256 == 2 * 2 * BM * CH, "table tile must split evenly");
     static_assert(NU >= 1, "operand tile too small");
-    __shared__ __attribute__((aligned(16))) unsigned short As[2][2][BM][LDK];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[2][2][BN][LDK];
+    // operand tiles As[p][h][i][kappa], Bs[p][h][j][kappa]; the direct form
+    // reuses the same LDS to stage its output tile
+    constexpr int NSMEM16 = 2 * 2 * (BM + BN) * LDK;
+    __shared__ __attribute__((aligned(16))) unsigned short smem16[NSMEM16];
+    auto As = reinterpret_cast<unsigned short(*)[2][BM][LDK]>(smem16);
+    auto Bs = reinterpret_cast<unsigned short(*)[2][BN][LDK]>(smem16 + 2 * 2 * BM * LDK);
 
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const GemmItem it = a.items[item];
@@ -676,24 +680,43 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
                     }
                 }
     } else {
-        float *spec = (float *)a.out;
+        // staged per column half as [field][n], written as contiguous runs
+        // (as in k_leg_mfma)
+        constexpr int FH = BN / 4, RS = 2 * BM + 1;
+        static_assert(FH * RS * 2 * 2 <= NSMEM16, "staged output half must fit the operand LDS");
+        float *st = reinterpret_cast<float *>(smem16);
+        float2 *spec = (float2 *)a.out;
+        const int nrel0 = 2 * row0;
+        const int nvalid = min(2 * BM, a.trunc - m - nrel0 + 1);
 #pragma unroll
-        for (int p = 0; p < 2; ++p)
+        for (int h = 0; h < 2; ++h) {
+            __syncthreads();
+            if ((wave & 1) == h) {
 #pragma unroll
-            for (int i = 0; i < FM; ++i)
+                for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int j = 0; j < FN; ++j)
+                    for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        int k = row0 + wr + i * 16 + 4 * (lane >> 4) + v;
-                        int c = col0 + wc + j * 16 + (lane & 15);
-                        int nrel = p + 2 * k;
-                        if (m + nrel <= a.trunc && c < ncol) {
-                            float val = acc[p][i][j][v] * unscale;
-                            if (m == 0 && (c & 1)) val = 0.f;
-                            spec[2 * ((int64_t)(c >> 1) * a.nspec + sb + nrel) + (c & 1)] = val;
-                        }
-                    }
+                        for (int j = 0; j < FN; ++j)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int k = wr + i * 16 + 4 * (lane >> 4) + v;
+                                const int cl = j * 16 + (lane & 15);
+                                float val = acc[p][i][j][v] * unscale;
+                                if (m == 0 && (cl & 1)) val = 0.f;
+                                st[((cl >> 1) * RS + p + 2 * k) * 2 + (cl & 1)] = val;
+                            }
+            }
+            __syncthreads();
+            const int fbase = col0 / 2 + h * FH;
+            for (int fl = wave; fl < FH; fl += 4) {
+                const int f = fbase + fl;
+                if (f >= a.nfld) break;
+                float2 *dst = spec + (int64_t)f * a.nspec + sb + nrel0;
+                for (int nr = lane; nr < nvalid; nr += 64)
+                    dst[nr] = float2{st[(fl * RS + nr) * 2], st[(fl * RS + nr) * 2 + 1]};
+            }
+        }
     }
 }
 
