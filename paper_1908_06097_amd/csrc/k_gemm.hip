@@ -96,19 +96,22 @@ struct __attribute__((aligned(2 * sizeof(T)))) Vec2 {
     T x, y;
 };
 
-template <typename T, int BM, int BN, int BK, bool INV>
-__global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
+template <typename T, int BM, int BN, int BK, bool INV, int NW = 4>
+__global__ __launch_bounds__(64 * NW, 2) void k_leg_mfma(GemmArgs a)
 {
-    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+    // NW waves as 2 x (NW / 2): rows split in two, columns in NW / 2
+    constexpr int NT = 64 * NW, NWN = NW / 2;
+    constexpr int WM = BM / 2, WN = BN / NWN, FM = WM / 16, FN = WN / 16;
+    static_assert(NW == 4 || NW == 8, "4 or 8 waves per block");
     constexpr int LDA = BM + 16, LDB = BN + 16;
     constexpr int VEC = 16 / sizeof(T);                 // elements per 16-byte table load
-    constexpr int NA = (2 * BK * BM) / (VEC * 256);     // table loads per thread per stage
+    constexpr int NA = (2 * BK * BM) / (VEC * NT);      // table loads per thread per stage
     // complex operand loads per thread per stage: INV reads BN/2 fields x 2 BK
     // coefficients, DIR reads BK rings x BN/2 fields (north and south each)
-    constexpr int NB = INV ? (BK * BN) / 256 : (BK * BN) / 512;
+    constexpr int NB = INV ? (BK * BN) / NT : (BK * BN) / (2 * NT);
     constexpr int NM = INV ? 1 : NB;  // ring metadata per thread (DIR)
-    static_assert(NA * VEC * 256 == 2 * BK * BM, "table tile must split evenly");
-    static_assert(NB * (INV ? 256 : 512) == BK * BN, "operand tile must split evenly");
+    static_assert(NA * VEC * NT == 2 * BK * BM, "table tile must split evenly");
+    static_assert(NB * (INV ? NT : 2 * NT) == BK * BN, "operand tile must split evenly");
     static_assert(BK == 16 && BN >= 32, "operand swizzle assumes 16-deep stages");
     typedef typename Acc<T>::type V;
     typedef T VecT __attribute__((ext_vector_type(VEC)));
@@ -126,7 +129,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
     const MBlock b = a.mb[m];
     const int row0 = it.tr * BM, col0 = it.tc * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
+    const int wr = (wave / NWN) * WM, wc = (wave % NWN) * WN;
     const int ncol = 2 * a.nfld;
     const int64_t pstride = (int64_t)b.Kp * b.Rp;
     const T *A0 = (const T *)a.tab + (INV ? b.off_kr : b.off_rk);
@@ -150,7 +153,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
     auto meta = [&](int kk, RingPair *mp, T *mq) {
 #pragma unroll
         for (int v = 0; v < NM; ++v) {
-            int r = kk + (tid + v * 256) / (BN / 2);
+            int r = kk + (tid + v * NT) / (BN / 2);
             // with 64 fields per tile a wave's ring is uniform: scalar loads
             if constexpr (BN / 2 == 64) r = __builtin_amdgcn_readfirstlane(r);
             RingPair o = {-1, -1};
@@ -168,7 +171,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
     auto load = [&](int kk) {
 #pragma unroll
         for (int v = 0; v < NA; ++v) {
-            int idx = tid + v * 256;
+            int idx = tid + v * NT;
             int p = idx / (BK * BM / VEC), rem = idx - p * (BK * BM / VEC);
             int q = rem / (BM / VEC), i = (rem - q * (BM / VEC)) * VEC;
             ra[v] = *reinterpret_cast<const VecT *>(A0 + p * pstride + (int64_t)(kk + q) * lda_g + row0 + i);
@@ -177,7 +180,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
             const Vec2<T> *spec = (const Vec2<T> *)a.in;
 #pragma unroll
             for (int v = 0; v < NB; ++v) {
-                int idx = tid + v * 256;
+                int idx = tid + v * NT;
                 int fl = idx / (2 * BK), t = idx - fl * (2 * BK);
                 int f = col0 / 2 + fl, nrel = 2 * kk + t;
                 Vec2<T> z = {T(0), T(0)};
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
             const Vec2<T> *four = (const Vec2<T> *)a.in;
 #pragma unroll
             for (int v = 0; v < NB; ++v) {
-                int idx = tid + v * 256;
+                int idx = tid + v * NT;
                 int cp = idx % (BN / 2);
                 int f = col0 / 2 + cp;
                 Vec2<T> gn = {T(0), T(0)}, gs = {T(0), T(0)};
@@ -205,7 +208,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
     auto store = [&](int buf) {
 #pragma unroll
         for (int v = 0; v < NA; ++v) {
-            int idx = tid + v * 256;
+            int idx = tid + v * NT;
             int p = idx / (BK * BM / VEC), rem = idx - p * (BK * BM / VEC);
             int q = rem / (BM / VEC), i = (rem - q * (BM / VEC)) * VEC;
             *reinterpret_cast<VecT *>(&As[buf][p][q][i]) = ra[v];
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
         if (INV) {
 #pragma unroll
             for (int v = 0; v < NB; ++v) {
-                int idx = tid + v * 256;
+                int idx = tid + v * NT;
                 int fl = idx / (2 * BK), t = idx - fl * (2 * BK);
                 int p = t & 1, q = t >> 1;
                 Vec2<T> z = rb0[v];
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
         } else {
 #pragma unroll
             for (int v = 0; v < NB; ++v) {
-                int idx = tid + v * 256;
+                int idx = tid + v * NT;
                 int q = idx / (BN / 2), cp = idx - q * (BN / 2);
                 const T w = mq1[v];
                 const Vec2<T> gn = rb0[v], gs = rb1[v];
@@ -359,7 +362,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             __syncthreads();  // the K loop's (or the previous half's) LDS reads are done
-            if ((wave & 1) == h) {
+            if ((wave % NWN) / (NWN / 2) == h) {
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -369,7 +372,8 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
                                 const int k = wr + i * 16 + acc_row<T>(lane, v);
-                                const int cl = j * 16 + (lane & 15);
+                                // column within the staged half
+                                const int cl = wc - h * (BN / 2) + j * 16 + (lane & 15);
                                 T val = acc[p][i][j][v];
                                 if (m == 0 && (cl & 1)) val = 0;
                                 smem[((cl >> 1) * RS + p + 2 * k) * 2 + (cl & 1)] = val;
@@ -377,7 +381,7 @@ __global__ __launch_bounds__(256, 2) void k_leg_mfma(GemmArgs a)
             }
             __syncthreads();
             const int fbase = col0 / 2 + h * FH;
-            for (int fl = wave; fl < FH; fl += 4) {
+            for (int fl = wave; fl < FH; fl += NW) {
                 const int f = fbase + fl;
                 if (f >= a.nfld) break;
                 Vec2<T> *dst = spec + (int64_t)f * a.nspec + sb + nrel0;
@@ -786,19 +790,19 @@ hipError_t launch_mfma(const Plan &p, const GemmArgs &a, int bm, int bn, hipStre
     const std::vector<GemmItem> &items = INV ? p.inv_items : p.dir_items;
     const int grid = (int)items.size();
     if (!check_items(p, items, INV, bm, bn, BK)) return hipErrorInvalidValue;
-#define SHTX_TILE(BM, BN)                                                  \
+#define SHTX_TILE(BM, BN, NW)                                              \
     if (bm == BM && bn == BN) {                                            \
-        k_leg_mfma<T, BM, BN, BK, INV><<<grid, 256, 0, s>>>(a);            \
+        k_leg_mfma<T, BM, BN, BK, INV, NW><<<grid, 64 * NW, 0, s>>>(a);    \
         return hipGetLastError();                                          \
     }
     if constexpr (sizeof(T) == 4) {
-        SHTX_TILE(128, 128)
-        SHTX_TILE(64, 128)
-        SHTX_TILE(128, 64)
+        SHTX_TILE(128, 128, 8)
+        SHTX_TILE(64, 128, 4)
+        SHTX_TILE(128, 64, 4)
     } else {
-        SHTX_TILE(64, 64)
-        SHTX_TILE(32, 64)
-        SHTX_TILE(64, 32)
+        SHTX_TILE(64, 64, 4)
+        SHTX_TILE(32, 64, 4)
+        SHTX_TILE(64, 32, 4)
     }
 #undef SHTX_TILE
     return hipErrorInvalidValue;
