@@ -797,11 +797,11 @@ hipError_t launch_mfma(const Plan &p, const GemmArgs &a, int bm, int bn, hipStre
     }
     if constexpr (sizeof(T) == 4) {
         SHTX_TILE(128, 128, 8)
-        SHTX_TILE(64, 128, 4)
-        SHTX_TILE(128, 64, 4)
+        SHTX_TILE(64, 128, 8)
+        SHTX_TILE(128, 64, 8)
     } else {
-        SHTX_TILE(64, 64, 4)
-        SHTX_TILE(32, 64, 4)
+        SHTX_TILE(64, 64, 8)
+        SHTX_TILE(32, 64, 8)
         SHTX_TILE(64, 32, 4)
     }
 #undef SHTX_TILE
