@@ -25,6 +25,7 @@
 // the device; this kernel's layout and algorithm are this library's own.
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include "fft_roots.h"
 #include "shtx_internal.h"
@@ -439,95 +440,109 @@ __host__ __device__ constexpr bool is_gp_radix(int R)
 }
 
 // General prime pass (radix p = pd.R, an odd prime, first pass so Ns = 1 and
-// no input twiddles).  With x_r the inputs of a butterfly,
-//   X_0 = x_0 + sum_r s_r,
-//   X_t, X_{p-t} = x_0 + sum_r (s_r cos(2 pi r t / p) -+ i d_r sin(2 pi r t / p)),
-// s_r = x_r + x_{p-r}, d_r = x_r - x_{p-r}, r = 1 .. (p-1)/2.  The pairs
-// (s_r, d_r) replace the inputs in LDS; each work item then forms the outputs
-// of one butterfly for a block of 4 consecutive t, stepping the roots by
-// e^{-2 pi i r / p} from a table of the p-th roots held in LDS, keeps them in
-// registers over a barrier (the pass is in place) and writes them.
+// no input twiddles), as matrix products on the matrix cores.  With x_r the
+// inputs of butterfly b, w = e^{-2 pi i / p}, H = (p - 1) / 2,
+//   X_t = x_0 + P_t + i Q_t,   X_{p-t} = x_0 + P_t - i Q_t,   t = 0 .. H,
+//   P_t = sum_{r=1}^{H} Re(w^{rt}) s_r,   Q_t = sum_{r=1}^{H} Im(w^{rt}) d_r,
+// s_r = x_r + x_{p-r}, d_r = x_r - x_{p-r}: two real products of an H x H
+// matrix (cosines, sines) with an H x (2 x butterflies) matrix whose columns
+// are the real and imaginary parts of s or d.  A wave computes 16 x 16 output
+// units (rows t, columns (butterfly, re|im)) with 16x16x4 MFMAs: the matrix
+// operand is read from a table of the p-th roots in LDS at index r t mod p,
+// the data operand forms s and d from the ring's LDS slots as it is read.
+// The units' results stay in registers over a barrier (the pass is in place);
+// X_t of butterfly j then goes to j p + t.
+typedef float gp_f32x4 __attribute__((ext_vector_type(4)));
+typedef double gp_f64x4 __attribute__((ext_vector_type(4)));
+__device__ inline gp_f32x4 gp_mfma(float a, float b, gp_f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline gp_f64x4 gp_mfma(double a, double b, gp_f64x4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <typename T>
+__device__ inline T ldr(unsigned a)
+{
+    return *(const __attribute__((address_space(3))) T *)((LdsByte *)fft_smem + a);
+}
+template <typename T>
+__device__ inline void str(unsigned a, T v)
+{
+    *(__attribute__((address_space(3))) T *)((LdsByte *)fft_smem + a) = v;
+}
+
 template <typename T, typename WPtr>
 __device__ __attribute__((noinline)) void gp_pass(int buf_off, int lbufp, int nf, PassDesc pd, WPtr W)
 {
-    constexpr unsigned CB = sizeof(C2<T>);
-    const int p = pd.R, H = (p - 1) / 2, nbf = pd.nbf, TB = gp_tblocks(p);
+    using V4 = typename std::conditional<sizeof(T) == 4, gp_f32x4, gp_f64x4>::type;
+    constexpr unsigned CB = sizeof(C2<T>), RB = sizeof(T);
+    constexpr int NWV = kFftThreads / 64;
+    const int p = pd.R, H = (p - 1) / 2, nbf = pd.nbf, nb = nf * nbf;
+    const int mt = gp_row_tiles(p), nunits = mt * gp_col_tiles(nb), ksteps = (H + 3) / 4;
     const int roots_off = buf_off + nf * lbufp;
-    // 1. e^{-2 pi i u / p} = W_L[u nbf]
+    // 1. w^u = W_L[u nbf], u < p
     for (int u = threadIdx.x; u < p; u += kFftThreads) stb<T>((unsigned)(roots_off + u) * CB, C2<T>{W[u * nbf].x, W[u * nbf].y});
-    // 2. slot r <- s_r, slot p - r <- d_r (each item owns one pair)
-    const int hn = H * nbf, na = nf * hn;
-    const unsigned mg_hn = div_magic(hn);
-    for (int e = threadIdx.x; e < na; e += kFftThreads) {
-        const int f = udiv(e, mg_hn), rem = e - f * hn;
-        const int r1 = udiv(rem, pd.mg_nbf), j = rem - r1 * nbf;
-        const int sl = buf_off + f * lbufp + j;
-        const unsigned ar = (unsigned)(sl + (r1 + 1) * nbf) * CB, ap = (unsigned)(sl + (p - 1 - r1) * nbf) * CB;
-        const C2<T> x = ldb<T>(ar), y = ldb<T>(ap);
-        stb<T>(ar, cadd(x, y));
-        stb<T>(ap, csub(x, y));
-    }
     __syncthreads();
-    // 3. outputs of each (field, butterfly, block of 4 t) item into registers
-    const int jt = nbf * TB, nb = nf * jt;
-    const unsigned mg_jt = div_magic(jt), mg_tb = div_magic(TB);
-    C2<T> out[kGpRounds][9];
-    int obase[kGpRounds], ot0[kGpRounds];
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, lr = lane & 15, lk = lane >> 4;
+    const unsigned rstep = 4u * nbf * CB;
+    V4 accp[kGpUnits], accq[kGpUnits];
+    T x0[kGpUnits];
+    // 2. units wave, wave + NWV, ...: rows t = 16 i + (0..15), columns
+    //    c = 16 g + (0..15) = 2 b + (re|im)
 #pragma unroll
-    for (int g = 0; g < kGpRounds; ++g) {
-        const int e = threadIdx.x + g * kFftThreads;
-        ot0[g] = -1;
-        if (e < nb) {
-            const int f = udiv(e, mg_jt), rem = e - f * jt;
-            const int j = udiv(rem, mg_tb), tb = rem - j * TB;
-            const int t0 = 1 + 4 * tb;
-            const int sl = buf_off + f * lbufp + j;
-            const C2<T> x0 = ldb<T>((unsigned)sl * CB);
-            C2<T> sum = x0, re[4] = {x0, x0, x0, x0}, im[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) im[q] = C2<T>{T(0), T(0)};
-            int u = 0;  // r t0 mod p
-            for (int r = 1; r <= H; ++r) {
-                u += t0;
+    for (int s = 0; s < kGpUnits; ++s) {
+        const int unit = wave + s * NWV;
+        if (unit < nunits) {
+            const int i = unit % mt, g = unit / mt;
+            const int t = 16 * i + lr;  // matrix operand row of this lane
+            int u = (t * (1 + lk)) % p;   // r t mod p for r = 1 + lk
+            const int du = (4 * t) % p;
+            const int c = 16 * g + lr;  // data operand column of this lane
+            const int b = min(c >> 1, nb - 1);
+            const int f = udiv(b, pd.mg_nbf), j = b - f * nbf;
+            const unsigned slot = (unsigned)(buf_off + f * lbufp + j) * CB + (unsigned)(c & 1) * RB;
+            unsigned ar = slot + (unsigned)(1 + lk) * nbf * CB, am = slot + (unsigned)(p - 1 - lk) * nbf * CB;
+            V4 P = {T(0), T(0), T(0), T(0)}, Q = {T(0), T(0), T(0), T(0)};
+            for (int k = 0; k < ksteps; ++k) {
+                const C2<T> w = ldb<T>((unsigned)(roots_off + u) * CB);
+                const T xr = ldr<T>(ar), xm = ldr<T>(am);
+                const bool live = 1 + 4 * k + lk <= H;
+                P = gp_mfma(w.x, live ? xr + xm : T(0), P);
+                Q = gp_mfma(w.y, live ? xr - xm : T(0), Q);
+                u += du;
                 if (u >= p) u -= p;
-                const C2<T> sr = ldb<T>((unsigned)(sl + r * nbf) * CB);
-                const C2<T> dr = ldb<T>((unsigned)(sl + (p - r) * nbf) * CB);
-                const C2<T> st = ldb<T>((unsigned)(roots_off + r) * CB);
-                C2<T> w = ldb<T>((unsigned)(roots_off + u) * CB);
-                sum = cadd(sum, sr);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (q > 0) w = cmul(w, st);  // e^{-2 pi i r (t0 + q) / p}
-                    re[q].x += sr.x * w.x;
-                    re[q].y += sr.y * w.x;
-                    im[q].x += dr.x * w.y;
-                    im[q].y += dr.y * w.y;
-                }
+                ar += rstep;
+                am -= rstep;
             }
-            out[g][0] = sum;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                out[g][1 + 2 * q] = C2<T>{re[q].x - im[q].y, re[q].y + im[q].x};  // X_{t0+q}
-                out[g][2 + 2 * q] = C2<T>{re[q].x + im[q].y, re[q].y - im[q].x};  // X_{p-t0-q}
-            }
-            obase[g] = buf_off + f * lbufp + j * p;
-            ot0[g] = t0;
+            accp[s] = P;
+            accq[s] = Q;
+            x0[s] = ldr<T>(slot);
         }
     }
     __syncthreads();
-    // 4. X_t of butterfly j goes to j p + t (Stockham output order at Ns = 1)
+    // 3. lane (column c, four rows) holds P and Q of one real component; i Q
+    //    takes the other component's Q from the neighbour lane.  Output rows of
+    //    the 16x16x4 MFMA: 4 (lane / 16) + v in FP32, lane / 16 + 4 v in FP64.
 #pragma unroll
-    for (int g = 0; g < kGpRounds; ++g) {
-        const int t0 = ot0[g];
-        if (t0 < 0) continue;
-        const int ob = obase[g];
-        if (t0 == 1) stb<T>((unsigned)ob * CB, out[g][0]);
+    for (int s = 0; s < kGpUnits; ++s) {
+        const int unit = wave + s * NWV;
+        if (unit < nunits) {
+            const int i = unit % mt, g = unit / mt;
+            const int c = 16 * g + lr, b = c >> 1, im = c & 1;
+            const int f = udiv(min(b, nb - 1), pd.mg_nbf), j = min(b, nb - 1) - f * nbf;
+            const unsigned ob = (unsigned)(buf_off + f * lbufp + j * p) * CB + (unsigned)im * RB;
+            const T sg = im ? T(1) : T(-1);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int t = t0 + q;
-            if (t > H) break;
-            stb<T>((unsigned)(ob + t) * CB, out[g][1 + 2 * q]);
-            stb<T>((unsigned)(ob + p - t) * CB, out[g][2 + 2 * q]);
+            for (int v = 0; v < 4; ++v) {
+                const T qo = __shfl_xor(accq[s][v], 1);
+                const int t = 16 * i + (sizeof(T) == 8 ? lk + 4 * v : 4 * lk + v);
+                if (b < nb && t <= H) {
+                    str<T>(ob + (unsigned)t * CB, x0[s] + accp[s][v] + sg * qo);
+                    if (t > 0) str<T>(ob + (unsigned)(p - t) * CB, x0[s] + accp[s][v] - sg * qo);
+                }
+            }
         }
     }
     __syncthreads();
@@ -831,11 +846,12 @@ bool check_fft(const Plan &p, int cap)
             if (R < 2 || d.L % R) SHTX_FFT_FAIL;
             if (is_gp_radix<T>(R)) {
                 // a general prime pass: the first pass only, an odd prime up to
-                // kGpMaxPrime, its results held for kGpRounds items per thread
+                // kGpMaxPrime, at most kGpUnits output units per wave
                 if (s != 0 || code != 0 || R > kGpMaxPrime || R % 2 == 0 || d.blue) SHTX_FFT_FAIL;
                 for (int q = 3; q * q <= R; q += 2)
                     if (R % q == 0) SHTX_FFT_FAIL;
-                if ((int64_t)d.fb * pd.nbf * gp_tblocks(R) > (int64_t)kGpRounds * kFftThreads) SHTX_FFT_FAIL;
+                if ((int64_t)gp_row_tiles(R) * gp_col_tiles(d.fb * pd.nbf) > (int64_t)kGpUnits * (kFftThreads / 64))
+                    SHTX_FFT_FAIL;
                 extra = kGpRootSlots;
             } else {
                 bool ok = R == 4 || R == 8;

@@ -193,15 +193,15 @@ int fft_blocking(Plan &p, int cap)
         if (d.lbuf > maxcap) return SHTX_EUNSUPPORTED;
         d.fb = std::max(1, std::min(F, cap / d.lbuf));
         // passes of radix 11 and up run one round of kFftThreads butterflies;
-        // a general prime pass keeps its outputs for kGpRounds rounds of
-        // (butterfly, block of 4 output pairs) items
+        // a general prime pass holds at most kGpUnits output units per wave
         int extra = 0;
         for (int s = 0; s < d.nrad; ++s) {
             const PassDesc &q = p.passes[d.pass_off + s];
             const int R = q.R;
             int lim;
             if (R > 23 || (p.prec == SHTX_FP64 && R > 17)) {
-                lim = kGpRounds * kFftThreads / (q.nbf * gp_tblocks(R));
+                // units = row tiles x ceil(2 fb nbf / 16)
+                lim = 8 * (kGpUnits * (kFftThreads / 64) / gp_row_tiles(R)) / q.nbf;
                 extra = kGpRootSlots;
             } else {
                 lim = fft_rounds(maxcap, R) * kFftThreads / q.nbf;
