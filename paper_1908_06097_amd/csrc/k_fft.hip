@@ -23,6 +23,7 @@
 //
 // The paper (Section 3.1.1) keeps fields resident on the device and packs on
 // the device; this kernel's layout and algorithm are this library's own.
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <type_traits>
@@ -256,6 +257,21 @@ constexpr int kU = 4;
 // times the LDS capacity).  magic 0 stands for d = 1.
 __device__ inline int udiv(int a, unsigned magic) { return magic ? (int)__umulhi((unsigned)a, magic) : a; }
 
+// Block-uniform values passed to the non-inlined pass functions arrive in
+// vector registers; these move them to scalar registers.
+__device__ inline int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline unsigned uni(unsigned x) { return (unsigned)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ inline PassDesc uniform(PassDesc d)
+{
+    d.R = uni(d.R);
+    d.Ns = uni(d.Ns);
+    d.nbf = uni(d.nbf);
+    d.tstep = uni(d.tstep);
+    d.mg_nbf = uni(d.mg_nbf);
+    d.mg_ns = uni(d.mg_ns);
+    return d;
+}
+
 
 // The table reads behind the twiddle powers of one butterfly: w = W[t1]
 // (w = exp(-2 pi i k / (Ns R))) and, for radix 9 and 16, w^3 or w^4.
@@ -467,54 +483,89 @@ __device__ inline T ldr(unsigned a)
 {
     return *(const __attribute__((address_space(3))) T *)((LdsByte *)fft_smem + a);
 }
+// Absolute LDS addresses (the dynamic LDS base already added), for loops that
+// step addresses instead of re-adding the base at every access.
+__device__ inline unsigned lds_base() { return (unsigned)(uintptr_t)(LdsByte *)fft_smem; }
+template <typename T>
+__device__ inline T lda(unsigned a)
+{
+    return *(const __attribute__((address_space(3))) T *)(uintptr_t)a;
+}
 template <typename T>
 __device__ inline void str(unsigned a, T v)
 {
     *(__attribute__((address_space(3))) T *)((LdsByte *)fft_smem + a) = v;
 }
 
-template <typename T, typename WPtr>
-__device__ __attribute__((noinline)) void gp_pass(int buf_off, int lbufp, int nf, PassDesc pd, WPtr W)
+template <typename T, bool TWL>
+__device__ __attribute__((noinline)) void gp_pass(int buf_off, int lbufp, int nf, PassDesc pd, GlobalC2<T> *Wg)
 {
     using V4 = typename std::conditional<sizeof(T) == 4, gp_f32x4, gp_f64x4>::type;
     constexpr unsigned CB = sizeof(C2<T>), RB = sizeof(T);
     constexpr int NWV = kFftThreads / 64;
+    pd = uniform(pd);
+    buf_off = uni(buf_off);
+    lbufp = uni(lbufp);
+    nf = uni(nf);
     const int p = pd.R, H = (p - 1) / 2, nbf = pd.nbf, nb = nf * nbf;
     const int mt = gp_row_tiles(p), nunits = mt * gp_col_tiles(nb), ksteps = (H + 3) / 4;
-    const int roots_off = buf_off + nf * lbufp;
-    // 1. w^u = W_L[u nbf], u < p
-    for (int u = threadIdx.x; u < p; u += kFftThreads) stb<T>((unsigned)(roots_off + u) * CB, C2<T>{W[u * nbf].x, W[u * nbf].y});
-    __syncthreads();
+    // 1. w^u at LDS byte rbase + u rstr: the LDS twiddle table W_L[u nbf]
+    //    (at offset 0), else a table of the p roots after the field slots
+    unsigned rbase = 0, rstr = nbf * CB;
+    if constexpr (!TWL) {
+        const int roots_off = buf_off + nf * lbufp;
+        for (int u = threadIdx.x; u < p; u += kFftThreads)
+            stb<T>((unsigned)(roots_off + u) * CB, C2<T>{Wg[u * nbf].x, Wg[u * nbf].y});
+        __syncthreads();
+        rbase = (unsigned)roots_off * CB;
+        rstr = CB;
+    }
+    const unsigned rspan = (unsigned)p * rstr, rstep = 4u * nbf * CB;
+    const unsigned lb = lds_base(), rb = lb + rbase;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, lr = lane & 15, lk = lane >> 4;
-    const unsigned rstep = 4u * nbf * CB;
-    V4 accp[kGpUnits], accq[kGpUnits];
-    T x0[kGpUnits];
+    constexpr int NU = gp_units(sizeof(T) == 8);
+    V4 accp[NU], accq[NU];
+    T x0[NU];
     // 2. units wave, wave + NWV, ...: rows t = 16 i + (0..15), columns
     //    c = 16 g + (0..15) = 2 b + (re|im)
 #pragma unroll
-    for (int s = 0; s < kGpUnits; ++s) {
+    for (int s = 0; s < NU; ++s) {
         const int unit = wave + s * NWV;
         if (unit < nunits) {
             const int i = unit % mt, g = unit / mt;
             const int t = 16 * i + lr;  // matrix operand row of this lane
-            int u = (t * (1 + lk)) % p;   // r t mod p for r = 1 + lk
-            const int du = (4 * t) % p;
+            // (r t mod p) rstr for r = 1 + lk, stepped by 4 t mod p and wrapped
+            // without a branch: min(x, x - span) in unsigned arithmetic
+            unsigned ur = (unsigned)((t * (1 + lk)) % p) * rstr;
+            const unsigned du = (unsigned)((4 * t) % p) * rstr;
             const int c = 16 * g + lr;  // data operand column of this lane
             const int b = min(c >> 1, nb - 1);
             const int f = udiv(b, pd.mg_nbf), j = b - f * nbf;
             const unsigned slot = (unsigned)(buf_off + f * lbufp + j) * CB + (unsigned)(c & 1) * RB;
-            unsigned ar = slot + (unsigned)(1 + lk) * nbf * CB, am = slot + (unsigned)(p - 1 - lk) * nbf * CB;
+            // absolute addresses of x_r and x_{p-r}, stepped by 4 rows
+            unsigned ar = lb + slot + (unsigned)(1 + lk) * nbf * CB, am = lb + slot + (unsigned)(p - 1 - lk) * nbf * CB;
             V4 P = {T(0), T(0), T(0), T(0)}, Q = {T(0), T(0), T(0), T(0)};
-            for (int k = 0; k < ksteps; ++k) {
-                const C2<T> w = ldb<T>((unsigned)(roots_off + u) * CB);
-                const T xr = ldr<T>(ar), xm = ldr<T>(am);
-                const bool live = 1 + 4 * k + lk <= H;
-                P = gp_mfma(w.x, live ? xr + xm : T(0), P);
-                Q = gp_mfma(w.y, live ? xr - xm : T(0), Q);
-                u += du;
-                if (u >= p) u -= p;
+            // operands of step k + 1 are read before the products of step k
+            C2<T> w = ldc<T>((const LdsC2<T> *)(uintptr_t)(rb + ur));
+            T xr = lda<T>(ar), xm = lda<T>(am);
+            for (int k = 0; k < ksteps - 1; ++k) {
+                const unsigned nx = ur + du;
+                ur = min(nx, nx - rspan);
                 ar += rstep;
                 am -= rstep;
+                const C2<T> w1 = ldc<T>((const LdsC2<T> *)(uintptr_t)(rb + ur));
+                const T xr1 = lda<T>(ar), xm1 = lda<T>(am);
+                P = gp_mfma(w.x, xr + xm, P);
+                Q = gp_mfma(w.y, xr - xm, Q);
+                w = w1;
+                xr = xr1;
+                xm = xm1;
+            }
+            {
+                // last step: rows r = 4 (ksteps - 1) + 1 + lk past H contribute 0
+                const bool live = 4 * (ksteps - 1) + 1 + lk <= H;
+                P = gp_mfma(w.x, live ? xr + xm : T(0), P);
+                Q = gp_mfma(w.y, live ? xr - xm : T(0), Q);
             }
             accp[s] = P;
             accq[s] = Q;
@@ -526,7 +577,7 @@ __device__ __attribute__((noinline)) void gp_pass(int buf_off, int lbufp, int nf
     //    takes the other component's Q from the neighbour lane.  Output rows of
     //    the 16x16x4 MFMA: 4 (lane / 16) + v in FP32, lane / 16 + 4 v in FP64.
 #pragma unroll
-    for (int s = 0; s < kGpUnits; ++s) {
+    for (int s = 0; s < NU; ++s) {
         const int unit = wave + s * NWV;
         if (unit < nunits) {
             const int i = unit % mt, g = unit / mt;
@@ -559,10 +610,7 @@ __device__ inline void pass_dispatch(int buf_off, int lbufp, int nf, const PassD
         return;
     }
     if (is_gp_radix<T>(pd.R)) {
-        if constexpr (TWL)
-            gp_pass<T>(buf_off, lbufp, nf, pd, (const LdsC2<T> *)lds_c2<T>());
-        else
-            gp_pass<T>(buf_off, lbufp, nf, pd, (GlobalC2<T> *)W);
+        gp_pass<T, TWL>(buf_off, lbufp, nf, pd, (GlobalC2<T> *)W);
         return;
     }
     switch (pd.R) {
@@ -846,13 +894,14 @@ bool check_fft(const Plan &p, int cap)
             if (R < 2 || d.L % R) SHTX_FFT_FAIL;
             if (is_gp_radix<T>(R)) {
                 // a general prime pass: the first pass only, an odd prime up to
-                // kGpMaxPrime, at most kGpUnits output units per wave
-                if (s != 0 || code != 0 || R > kGpMaxPrime || R % 2 == 0 || d.blue) SHTX_FFT_FAIL;
+                // gp_max_prime, at most gp_units output units per wave
+                if (s != 0 || code != 0 || R > gp_max_prime(sizeof(T) == 8) || R % 2 == 0 || d.blue) SHTX_FFT_FAIL;
                 for (int q = 3; q * q <= R; q += 2)
                     if (R % q == 0) SHTX_FFT_FAIL;
-                if ((int64_t)gp_row_tiles(R) * gp_col_tiles(d.fb * pd.nbf) > (int64_t)kGpUnits * (kFftThreads / 64))
+                if ((int64_t)gp_row_tiles(R) * gp_col_tiles(d.fb * pd.nbf) >
+                    (int64_t)gp_units(sizeof(T) == 8) * (kFftThreads / 64))
                     SHTX_FFT_FAIL;
-                extra = kGpRootSlots;
+                extra = R;
             } else {
                 bool ok = R == 4 || R == 8;
                 for (int q : {2, 3, 5, 7, 9, 11, 13, 16, 17}) ok = ok || R == q;

@@ -193,7 +193,7 @@ int fft_blocking(Plan &p, int cap)
         if (d.lbuf > maxcap) return SHTX_EUNSUPPORTED;
         d.fb = std::max(1, std::min(F, cap / d.lbuf));
         // passes of radix 11 and up run one round of kFftThreads butterflies;
-        // a general prime pass holds at most kGpUnits output units per wave
+        // a general prime pass holds at most gp_units output units per wave
         int extra = 0;
         for (int s = 0; s < d.nrad; ++s) {
             const PassDesc &q = p.passes[d.pass_off + s];
@@ -201,8 +201,8 @@ int fft_blocking(Plan &p, int cap)
             int lim;
             if (R > 23 || (p.prec == SHTX_FP64 && R > 17)) {
                 // units = row tiles x ceil(2 fb nbf / 16)
-                lim = 8 * (kGpUnits * (kFftThreads / 64) / gp_row_tiles(R)) / q.nbf;
-                extra = kGpRootSlots;
+                lim = 8 * (gp_units(p.prec == SHTX_FP64) * (kFftThreads / 64) / gp_row_tiles(R)) / q.nbf;
+                extra = R;
             } else {
                 lim = fft_rounds(maxcap, R) * kFftThreads / q.nbf;
             }
@@ -346,25 +346,31 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         std::vector<int> f;
         const int maxp = dbl ? 17 : 23;
         const int rem = smooth_factor(h, f, maxp);
-        // one prime factor above the register radices, up to kGpMaxPrime, is
+        // Bluestein length: the smallest 2^a 3^b >= 2h - 1 with 9 | L
+        // (radix-16/9 passes; the leading radix-9 passes keep the power-of-two
+        // passes' LDS writes off a single bank)
+        int Lb = 2 * h - 1;
+        auto ok23 = [](int x) {
+            int threes = 0;
+            while (x % 2 == 0) x /= 2;
+            while (x % 3 == 0) x /= 3, ++threes;
+            return x == 1 && threes >= 2;
+        };
+        while (!ok23(Lb)) ++Lb;
+        // one prime factor above the register radices, up to gp_max_prime, is
         // run as a general prime pass (first, at Ns = 1) instead of Bluestein
-        const bool gp = rem > 1 && rem <= kGpMaxPrime && is_prime(rem);
+        // when one field's output units fit the block's waves and, above 191,
+        // when the cost model of the two (fitted to single-precision ring
+        // FFT timings on MI355X, in ps per grid point: prime pass
+        // 3.2 + 0.0086 p, Bluestein 0.37 (L / h) log2 L) favours it
+        bool gp = rem > 1 && rem <= gp_max_prime(dbl) && is_prime(rem) &&
+                  gp_row_tiles(rem) * gp_col_tiles(h / rem) <= gp_units(dbl) * (kFftThreads / 64);
+        if (gp && rem > 191) gp = 3.2 + 0.0086 * rem < 0.37 * Lb / h * std::log2((double)Lb);
         if (rem == 1 || gp) {
             lp.L = h;
             lp.blue = 0;
         } else {
-            // Bluestein length: the smallest 2^a 3^b >= 2h - 1 with 9 | L
-            // (radix-16/9 passes; the leading radix-9 passes keep the
-            // power-of-two passes' LDS writes off a single bank)
-            int L = 2 * h - 1;
-            auto ok23 = [](int x) {
-                int threes = 0;
-                while (x % 2 == 0) x /= 2;
-                while (x % 3 == 0) x /= 3, ++threes;
-                return x == 1 && threes >= 2;
-            };
-            while (!ok23(L)) ++L;
-            lp.L = L;
+            lp.L = Lb;
             lp.blue = 1;
         }
         if (std::max(lp.L, h + 1) > cap) return SHTX_EUNSUPPORTED;
