@@ -361,6 +361,10 @@ __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lb
     constexpr int NB = fft_rounds(CAP, R);
     constexpr int C2ND = twiddle_step2<R>();
     constexpr unsigned CB = sizeof(C2<T>);
+    pd = uniform(pd);
+    buf_off = uni(buf_off);
+    lbufp = uni(lbufp);
+    nf = uni(nf);
     const int nbf = pd.nbf, total = nf * nbf, Ns = pd.Ns;
     const unsigned srd = nbf * CB, swr = Ns * CB;  // byte strides of a butterfly's reads and writes
     // radices above 19 run a streamed butterfly: twiddles by stepping from
@@ -700,6 +704,8 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
         return d.blue ? cmul(u, chp) : u;
     };
     const int hp = h / 2 + 1, nmerge = nf * hp;
+    const unsigned nfld = (unsigned)a.nfld;
+    const C2<T> *fourb = four + f0;  // (m, f) at fourb[m nfld + f]
     for (int e0 = threadIdx.x; e0 < nmerge; e0 += kU * kFftThreads) {
         C2<T> ym[kU], yh[kU], pm[kU], ph[kU], cm[kU], ch[kU];
         int mm[kU], ff[kU];
@@ -714,15 +720,16 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
             const C2<T> zero = {T(0), T(0)};
             ym[u] = zero;
             yh[u] = zero;
-            if (ok && m <= M) ym[u] = four[(int64_t)m * a.nfld + f0 + f];
-            if (ok && h - m <= M) yh[u] = four[(int64_t)(h - m) * a.nfld + f0 + f];
-            pm[u] = post[m];
-            ph[u] = post[h - m];
+            // 32-bit unsigned element offsets from the block's base pointers
+            if (ok && m <= M) ym[u] = fourb[(unsigned)m * nfld + (unsigned)f];
+            if (ok && h - m <= M) yh[u] = fourb[(unsigned)(h - m) * nfld + (unsigned)f];
+            pm[u] = post[(unsigned)m];
+            ph[u] = post[(unsigned)(h - m)];
             cm[u] = zero;
             ch[u] = zero;
             if (d.blue) {
-                cm[u] = chirp[m];
-                ch[u] = chirp[m == 0 ? 0 : h - m];
+                cm[u] = chirp[(unsigned)m];
+                ch[u] = chirp[(unsigned)(m == 0 ? 0 : h - m)];
             }
         }
 #pragma unroll
@@ -753,7 +760,8 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
     dft_h<T, CAP, TWL>(buf_off, d, a.passes, nf, W, bhat);
     // 3. z = conj(DFT(u)): even samples Re z, odd samples Im z
     const T scale = a.adjoint ? T(d.w / (2.0 * d.n)) : T(1);
-    T *grid = (T *)a.out;
+    const unsigned npts = (unsigned)a.npts;
+    T *gridb = (T *)a.out + (uint64_t)f0 * npts + d.grid_off;  // field f at gridb + f npts
     const unsigned mg_h = div_magic(h);
     for (int e0 = threadIdx.x; e0 < nf * h; e0 += kU * kFftThreads) {
         C2<T> cp[kU];
@@ -761,7 +769,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
         for (int u = 0; u < kU; ++u) {
             const int e = e0 + u * kFftThreads;
             const int k = e < nf * h ? e - udiv(e, mg_h) * h : 0;
-            cp[u] = d.blue ? chirp[k] : C2<T>{T(1), T(0)};
+            cp[u] = d.blue ? chirp[(unsigned)k] : C2<T>{T(1), T(0)};
         }
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
@@ -771,7 +779,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
             const C2<T> x = ldc(buf + f * lbufp + k);
             const C2<T> r = d.blue ? cmul(cp[u], cconj(x)) : x;
             const C2<T> g = {scale * r.x, -scale * r.y};
-            *reinterpret_cast<C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k) = g;
+            *reinterpret_cast<C2<T> *>(gridb + (uint64_t)(unsigned)f * npts + 2u * (unsigned)k) = g;
         }
     }
 }
@@ -789,7 +797,8 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
     const C2<T> *post = tw + d.post_off;
     const C2<T> *chirp = tw + d.chirp_off, *bhat = tw + d.bhat_off;
     const int nf = it.nf, f0 = it.f0, h = d.h, M = d.M, lbufp = d.lbufp;
-    const T *grid = (const T *)a.in;
+    const unsigned npts = (unsigned)a.npts;
+    const T *gridb = (const T *)a.in + (uint64_t)f0 * npts + d.grid_off;  // field f at gridb + f npts
     int buf_off = 0;
     if (TWL) {
         for (int k = threadIdx.x; k < d.L; k += kFftThreads) stc(buf + k, W[k]);
@@ -810,8 +819,8 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
             if (e < nf * span) {
                 const int f = udiv(e, mg_span), k = e - f * span;
                 if (k < h) {
-                    z[u] = *reinterpret_cast<const C2<T> *>(grid + (int64_t)(f0 + f) * a.npts + d.grid_off + 2 * k);
-                    if (d.blue) cp[u] = chirp[k];
+                    z[u] = *reinterpret_cast<const C2<T> *>(gridb + (uint64_t)(unsigned)f * npts + 2u * (unsigned)k);
+                    if (d.blue) cp[u] = chirp[(unsigned)k];
                 }
             }
         }
@@ -827,7 +836,8 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
     dft_h<T, CAP, TWL>(buf_off, d, a.passes, nf, W, bhat);
     // 2. split: Y_m = (Z_m + conj Z_{h-m}) / 2 - (i/2) e^{-2 pi i m / n} (Z_m - conj Z_{h-m})
     const T scale = a.adjoint ? T(1) : T(1.0 / d.n);
-    C2<T> *four = (C2<T> *)a.out + d.four_off;
+    C2<T> *fourb = (C2<T> *)a.out + d.four_off + f0;  // (m, f) at fourb[m nfld + f]
+    const unsigned nfld = (unsigned)a.nfld;
     const unsigned mg_nf = div_magic(nf);
     const int nout = nf * (M + 1);
     for (int e0 = threadIdx.x; e0 < nout; e0 += kU * kFftThreads) {
@@ -836,12 +846,12 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
         for (int u = 0; u < kU; ++u) {
             const int e = e0 + u * kFftThreads;
             const int m = e < nout ? udiv(e, mg_nf) : 0;
-            pm[u] = post[m];
+            pm[u] = post[(unsigned)m];
             cm[u] = C2<T>{T(1), T(0)};
             ch[u] = C2<T>{T(1), T(0)};
             if (d.blue) {
-                cm[u] = chirp[m];
-                ch[u] = chirp[m == 0 ? 0 : h - m];
+                cm[u] = chirp[(unsigned)m];
+                ch[u] = chirp[(unsigned)(m == 0 ? 0 : h - m)];
             }
         }
 #pragma unroll
@@ -858,7 +868,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
             C2<T> y = {T(0.5) * (A.x + t.y), T(0.5) * (A.y - t.x)};
             T fac = (a.adjoint && m > 0) ? T(2) : T(1);
             y = {y.x * scale * fac, m == 0 ? T(0) : y.y * scale * fac};
-            four[(int64_t)m * a.nfld + f0 + f] = y;
+            fourb[(unsigned)m * nfld + (unsigned)f] = y;
         }
     }
 }
@@ -883,6 +893,9 @@ bool check_fft(const Plan &p, int cap)
             SHTX_FFT_FAIL;
         if (d.grid_off + d.n > p.npts || d.four_off + (int64_t)(d.M + 1) * p.nfld > p.nfour * p.nfld)
             SHTX_FFT_FAIL;
+        // the kernels index a field's grid row and a ring's Fourier rows with
+        // 32-bit unsigned element offsets
+        if (p.npts >= (int64_t(1) << 32) || (int64_t)(d.M + 1) * p.nfld >= (int64_t(1) << 32)) SHTX_FFT_FAIL;
         if (d.pass_off < 0 || d.pass_off + d.nrad > (int)p.passes.size() || d.nrad < 1) SHTX_FFT_FAIL;
         // the second Bluestein FFT applies the filter in a radix-9 first pass
         if (d.blue && p.passes[d.pass_off].R != 9) SHTX_FFT_FAIL;
