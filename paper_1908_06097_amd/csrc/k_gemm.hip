@@ -783,13 +783,28 @@ bool check_items_impl(const Plan &p, const std::vector<GemmItem> &items, bool in
     return true;
 }
 
-
-template <typename T, int BK, bool INV>
-hipError_t launch_mfma(const Plan &p, const GemmArgs &a, int bm, int bn, hipStream_t s)
+// A work list's main part with bm x bn tiles and its tail part (if any) with
+// bm x tail_bn tiles.
+bool check_work_list(const Plan &p, const std::vector<GemmItem> &items, int nmain, bool inverse_shape, int bm,
+                     int bn, int tail_bn, int bk)
 {
-    const std::vector<GemmItem> &items = INV ? p.inv_items : p.dir_items;
-    const int grid = (int)items.size();
-    if (!check_items(p, items, INV, bm, bn, BK)) return hipErrorInvalidValue;
+    if (nmain < 1 || nmain > (int)items.size()) return false;
+    const std::vector<GemmItem> main(items.begin(), items.begin() + nmain);
+    if (!check_items(p, main, inverse_shape, bm, bn, bk)) return false;
+    if (nmain == (int)items.size()) return true;
+    if (tail_bn <= 0) return false;
+    const std::vector<GemmItem> tail(items.begin() + nmain, items.end());
+    return check_items(p, tail, inverse_shape, bm, tail_bn, bk);
+}
+
+
+// One launch over items [first, first + count) of a work list, tiles bm x bn.
+template <typename T, int BK, bool INV>
+hipError_t launch_mfma_part(const GemmArgs &args, int first, int count, int bm, int bn, hipStream_t s)
+{
+    GemmArgs a = args;
+    a.items += first;
+    const int grid = count;
 #define SHTX_TILE(BM, BN, NW)                                              \
     if (bm == BM && bn == BN) {                                            \
         k_leg_mfma<T, BM, BN, BK, INV, NW><<<grid, 64 * NW, 0, s>>>(a);    \
@@ -806,6 +821,17 @@ hipError_t launch_mfma(const Plan &p, const GemmArgs &a, int bm, int bn, hipStre
     }
 #undef SHTX_TILE
     return hipErrorInvalidValue;
+}
+
+template <typename T, int BK, bool INV>
+hipError_t launch_mfma(const Plan &p, const GemmArgs &a, int bm, int bn, hipStream_t s)
+{
+    const std::vector<GemmItem> &items = INV ? p.inv_items : p.dir_items;
+    const int nmain = INV ? p.inv_nmain : p.dir_nmain, tail_bn = INV ? p.inv_tail_bn : p.dir_tail_bn;
+    if (!check_work_list(p, items, nmain, INV, bm, bn, tail_bn, BK)) return hipErrorInvalidValue;
+    hipError_t e = launch_mfma_part<T, BK, INV>(a, 0, nmain, bm, bn, s);
+    if (e != hipSuccess || nmain == (int)items.size()) return e;
+    return launch_mfma_part<T, BK, INV>(a, nmain, (int)items.size() - nmain, bm, tail_bn, s);
 }
 
 template <bool INV>
@@ -854,8 +880,9 @@ bool gemm_shapes_ok(const Plan &p)
     int bk = p.prec == SHTX_BF16X3 ? 32 : 16;
     if (!gemm_tile_supported(p.prec, p.inv_bm, p.inv_bn) || !gemm_tile_supported(p.prec, p.dir_bm, p.dir_bn))
         return false;
-    bool inv_ok = p.inv_items.empty() || check_items(p, p.inv_items, true, p.inv_bm, p.inv_bn, bk);
-    return inv_ok && check_items(p, p.dir_items, false, p.dir_bm, p.dir_bn, bk);
+    bool inv_ok = p.inv_items.empty() ||
+                  check_work_list(p, p.inv_items, p.inv_nmain, true, p.inv_bm, p.inv_bn, p.inv_tail_bn, bk);
+    return inv_ok && check_work_list(p, p.dir_items, p.dir_nmain, false, p.dir_bm, p.dir_bn, p.dir_tail_bn, bk);
 }
 
 hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, hipStream_t s)

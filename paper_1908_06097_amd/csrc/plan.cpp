@@ -235,29 +235,62 @@ int gemm_work_lists(Plan &p)
         return SHTX_EUNSUPPORTED;
     if (kTablePad % p.inv_bm || kTablePad % p.dir_bm) return SHTX_EUNSUPPORTED;
     const int N = p.trunc, ncol = 2 * p.nfld;
-    std::vector<std::vector<GemmItem>> gi, gd;
-    std::vector<double> ci, cd;
+    // a 128-column tile shape whose last column tile would hold at most 64
+    // valid columns covers those with one 64-column tile (FP32 has a 128 x 64
+    // kernel) in a second launch
+    auto tail_of = [&](int bm, int bn) {
+        return p.prec == SHTX_FP32 && bm == 128 && bn == 128 && ncol > 128 && ncol % 128 != 0 && ncol % 128 <= 64
+                   ? 64
+                   : 0;
+    };
+    p.inv_tail_bn = tail_of(p.inv_bm, p.inv_bn);
+    p.dir_tail_bn = tail_of(p.dir_bm, p.dir_bn);
+    std::vector<std::vector<GemmItem>> gi, gd, ti, td;
+    std::vector<double> ci, cd, cti, ctd;
     for (int m = 0; m <= N; ++m) {
         const MBlock &b = p.mb[m];
         double cost = (double)std::max(b.R, 1) * (N - m + 1) * ncol;
-        std::vector<GemmItem> a, c;
-        int ntc_i = (ncol + p.inv_bn - 1) / p.inv_bn;
+        std::vector<GemmItem> a, c, at, ct;
+        // main column tiles, then the tail tile's index in units of tail_bn
+        int ntc_i = p.inv_tail_bn ? ncol / p.inv_bn : (ncol + p.inv_bn - 1) / p.inv_bn;
         int ntr_i = (b.R + p.inv_bm - 1) / p.inv_bm;
-        for (int tr = 0; tr < ntr_i; ++tr)
+        for (int tr = 0; tr < ntr_i; ++tr) {
             for (int tc = 0; tc < ntc_i; ++tc) a.push_back(GemmItem{m, tr, tc, 0});
-        int ntc_d = (ncol + p.dir_bn - 1) / p.dir_bn;
+            if (p.inv_tail_bn) at.push_back(GemmItem{m, tr, ntc_i * p.inv_bn / p.inv_tail_bn, 0});
+        }
+        int ntc_d = p.dir_tail_bn ? ncol / p.dir_bn : (ncol + p.dir_bn - 1) / p.dir_bn;
         int ntk_d = (b.K0 + p.dir_bm - 1) / p.dir_bm;
-        for (int tk = 0; tk < ntk_d; ++tk)
+        for (int tk = 0; tk < ntk_d; ++tk) {
             for (int tc = 0; tc < ntc_d; ++tc) c.push_back(GemmItem{m, tk, tc, 0});
+            if (p.dir_tail_bn) ct.push_back(GemmItem{m, tk, ntc_d * p.dir_bn / p.dir_tail_bn, 0});
+        }
         if (!a.empty()) {
             gi.push_back(a);
             ci.push_back(cost);
+            if (!at.empty()) {
+                ti.push_back(at);
+                cti.push_back(cost);
+            }
         }
         gd.push_back(c);
         cd.push_back(cost);
+        if (!ct.empty()) {
+            td.push_back(ct);
+            ctd.push_back(cost);
+        }
     }
     p.inv_items = layout_by_xcd(gi, ci, GemmItem{-1, 0, 0, 0});
     p.dir_items = layout_by_xcd(gd, cd, GemmItem{-1, 0, 0, 0});
+    p.inv_nmain = (int)p.inv_items.size();
+    p.dir_nmain = (int)p.dir_items.size();
+    if (!ti.empty()) {
+        std::vector<GemmItem> t = layout_by_xcd(ti, cti, GemmItem{-1, 0, 0, 0});
+        p.inv_items.insert(p.inv_items.end(), t.begin(), t.end());
+    }
+    if (!td.empty()) {
+        std::vector<GemmItem> t = layout_by_xcd(td, ctd, GemmItem{-1, 0, 0, 0});
+        p.dir_items.insert(p.dir_items.end(), t.begin(), t.end());
+    }
     return SHTX_OK;
 }
 

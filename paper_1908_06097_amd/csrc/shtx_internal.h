@@ -119,7 +119,11 @@ struct Plan {
 
     // GEMM tiling chosen at plan time (depends on precision).
     int inv_bm = 0, inv_bn = 0, dir_bm = 0, dir_bn = 0;
+    // Each work list is its main part (tiles of bm x bn) followed, when the
+    // last column tile would be less than half used, by a tail part whose
+    // tiles are tail_bn columns wide; nmain counts the main part's items.
     std::vector<GemmItem> inv_items, dir_items;
+    int inv_nmain = 0, dir_nmain = 0, inv_tail_bn = 0, dir_tail_bn = 0;
     std::vector<FftItem> fft_items;
     std::vector<PassDesc> passes;
     int fft_lds_bytes = 0;
