@@ -439,17 +439,13 @@ __device__ __attribute__((noinline)) void stockham_pass_impl(int buf_off, int lb
     __syncthreads();
 }
 
-// Twiddles from LDS (TWL) or from the global table, each through a typed
-// pointer so that the pass uses ds_* or global_* instructions.
-template <typename T, int R, int CAP, bool TWL, bool BHAT>
+// Twiddles and filter from the global tables (L1/L2 resident), through
+// global-address-space pointers so that the pass uses global_* loads.
+template <typename T, int R, int CAP, bool BHAT>
 __device__ inline void stockham_pass(int buf_off, int lbufp, int nf, const PassDesc &pd, const C2<T> *Wg,
                                      const C2<T> *bhat)
 {
-    if constexpr (TWL)
-        stockham_pass_impl<T, R, CAP, BHAT>(buf_off, lbufp, nf, pd, (const LdsC2<T> *)lds_c2<T>(),
-                                            (GlobalC2<T> *)bhat);
-    else
-        stockham_pass_impl<T, R, CAP, BHAT>(buf_off, lbufp, nf, pd, (GlobalC2<T> *)Wg, (GlobalC2<T> *)bhat);
+    stockham_pass_impl<T, R, CAP, BHAT>(buf_off, lbufp, nf, pd, (GlobalC2<T> *)Wg, (GlobalC2<T> *)bhat);
 }
 
 // Radices above the register butterflies run as the general prime pass.
@@ -501,7 +497,7 @@ __device__ inline void str(unsigned a, T v)
     *(__attribute__((address_space(3))) T *)((LdsByte *)fft_smem + a) = v;
 }
 
-template <typename T, bool TWL>
+template <typename T>
 __device__ __attribute__((noinline)) void gp_pass(int buf_off, int lbufp, int nf, PassDesc pd, GlobalC2<T> *Wg)
 {
     using V4 = typename std::conditional<sizeof(T) == 4, gp_f32x4, gp_f64x4>::type;
@@ -513,17 +509,12 @@ __device__ __attribute__((noinline)) void gp_pass(int buf_off, int lbufp, int nf
     nf = uni(nf);
     const int p = pd.R, H = (p - 1) / 2, nbf = pd.nbf, nb = nf * nbf;
     const int mt = gp_row_tiles(p), nunits = mt * gp_col_tiles(nb), ksteps = (H + 3) / 4;
-    // 1. w^u at LDS byte rbase + u rstr: the LDS twiddle table W_L[u nbf]
-    //    (at offset 0), else a table of the p roots after the field slots
-    unsigned rbase = 0, rstr = nbf * CB;
-    if constexpr (!TWL) {
-        const int roots_off = buf_off + nf * lbufp;
-        for (int u = threadIdx.x; u < p; u += kFftThreads)
-            stb<T>((unsigned)(roots_off + u) * CB, C2<T>{Wg[u * nbf].x, Wg[u * nbf].y});
-        __syncthreads();
-        rbase = (unsigned)roots_off * CB;
-        rstr = CB;
-    }
+    // 1. w^u = W_L[u nbf] (u < p) to a table of p roots after the field slots
+    const int roots_off = buf_off + nf * lbufp;
+    for (int u = threadIdx.x; u < p; u += kFftThreads)
+        stb<T>((unsigned)(roots_off + u) * CB, C2<T>{Wg[u * nbf].x, Wg[u * nbf].y});
+    __syncthreads();
+    const unsigned rbase = (unsigned)roots_off * CB, rstr = CB;
     const unsigned rspan = (unsigned)p * rstr, rstep = 4u * nbf * CB;
     const unsigned lb = lds_base(), rb = lb + rbase;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, lr = lane & 15, lk = lane >> 4;
@@ -603,41 +594,41 @@ __device__ __attribute__((noinline)) void gp_pass(int buf_off, int lbufp, int nf
     __syncthreads();
 }
 
-template <typename T, int CAP, bool TWL, bool BHAT>
+template <typename T, int CAP, bool BHAT>
 __device__ inline void pass_dispatch(int buf_off, int lbufp, int nf, const PassDesc &pd, const C2<T> *W,
                                      const C2<T> *bhat)
 {
     if constexpr (BHAT) {
         // Bluestein lengths are 2^a 3^b with 9 | L and the radix-9 passes first
         // (checked on the host), so the filter pass is always radix 9
-        stockham_pass<T, 9, CAP, TWL, true>(buf_off, lbufp, nf, pd, W, bhat);
+        stockham_pass<T, 9, CAP, true>(buf_off, lbufp, nf, pd, W, bhat);
         return;
     }
     if (is_gp_radix<T>(pd.R)) {
-        gp_pass<T, TWL>(buf_off, lbufp, nf, pd, (GlobalC2<T> *)W);
+        gp_pass<T>(buf_off, lbufp, nf, pd, (GlobalC2<T> *)W);
         return;
     }
     switch (pd.R) {
-    case 2: stockham_pass<T, 2, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
-    case 3: stockham_pass<T, 3, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
-    case 4: stockham_pass<T, 4, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
-    case 5: stockham_pass<T, 5, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
-    case 7: stockham_pass<T, 7, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
-    case 11: stockham_pass<T, 11, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
-    case 13: stockham_pass<T, 13, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
-    case 17: stockham_pass<T, 17, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 2: stockham_pass<T, 2, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 3: stockham_pass<T, 3, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 4: stockham_pass<T, 4, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 5: stockham_pass<T, 5, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 7: stockham_pass<T, 7, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 11: stockham_pass<T, 11, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 13: stockham_pass<T, 13, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 17: stockham_pass<T, 17, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
     // FP64 plans stop at radix 17 (larger FP64 butterflies would not fit the
     // registers); the host never plans the radices below for them
     case 19:
-        if constexpr (sizeof(T) == 4) stockham_pass<T, 19, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat);
+        if constexpr (sizeof(T) == 4) stockham_pass<T, 19, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat);
         break;
     case 23:
-        if constexpr (sizeof(T) == 4) stockham_pass<T, 23, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat);
+        if constexpr (sizeof(T) == 4) stockham_pass<T, 23, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat);
         break;
 
-    case 9: stockham_pass<T, 9, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
-    case 16: stockham_pass<T, 16, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
-    default: stockham_pass<T, 8, CAP, TWL, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 9: stockham_pass<T, 9, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    case 16: stockham_pass<T, 16, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
+    default: stockham_pass<T, 8, CAP, BHAT>(buf_off, lbufp, nf, pd, W, bhat); break;
     }
 }
 
@@ -647,27 +638,27 @@ __device__ inline void pass_dispatch(int buf_off, int lbufp, int nf, const PassD
 // applies the filter (conj(X bhat)) to the first FFT's output, the second FFT
 // leaves conj(conv), and the caller multiplies by the chirp when reading the
 // first h outputs.
-template <typename T, int CAP, bool TWL>
+template <typename T, int CAP>
 __device__ void dft_h(int buf_off, const RingDesc &d, const PassDesc *passes, int nf, const C2<T> *W,
                       const C2<T> *bhat)
 {
     const PassDesc *ps = passes + d.pass_off;
     for (int s = 0; s < d.nrad; ++s) {
         const PassDesc pd = ps[s];
-        pass_dispatch<T, CAP, TWL, false>(buf_off, d.lbufp, nf, pd, W, bhat);
+        pass_dispatch<T, CAP, false>(buf_off, d.lbufp, nf, pd, W, bhat);
     }
     if (d.blue)
         for (int s = 0; s < d.nrad; ++s) {
             const PassDesc pd = ps[s];
             if (s == 0)
-                pass_dispatch<T, CAP, TWL, true>(buf_off, d.lbufp, nf, pd, W, bhat);
+                pass_dispatch<T, CAP, true>(buf_off, d.lbufp, nf, pd, W, bhat);
             else
-                pass_dispatch<T, CAP, TWL, false>(buf_off, d.lbufp, nf, pd, W, bhat);
+                pass_dispatch<T, CAP, false>(buf_off, d.lbufp, nf, pd, W, bhat);
         }
 }
 
 
-template <typename T, int CAP, bool TWL>
+template <typename T, int CAP>
 __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
 {
     LdsC2<T> *buf = lds_c2<T>();
@@ -683,13 +674,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
     const C2<T> *four = (const C2<T> *)a.in + d.four_off;
     const T facpos = a.adjoint ? T(0.5) : T(1);
     const unsigned mg_nf = div_magic(nf);
-    int buf_off = 0;
-    if (TWL) {
-        // the length-L twiddle table goes to LDS ahead of the field slots
-        for (int k = threadIdx.x; k < d.L; k += kFftThreads) stc(buf + k, W[k]);
-        buf_off = d.L;
-        buf += d.L;
-    }
+    const int buf_off = 0;
 
     // 1. read the kept coefficients Y_m, Y_{h-m} (m <= M) and merge them into
     //    the length-h sequence u = conj(Z'), Z'_m = (Y_m + conj Y_{h-m})
@@ -757,7 +742,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
     }
     __syncthreads();
     // 2. forward DFT of length h
-    dft_h<T, CAP, TWL>(buf_off, d, a.passes, nf, W, bhat);
+    dft_h<T, CAP>(buf_off, d, a.passes, nf, W, bhat);
     // 3. z = conj(DFT(u)): even samples Re z, odd samples Im z
     const T scale = a.adjoint ? T(d.w / (2.0 * d.n)) : T(1);
     const unsigned npts = (unsigned)a.npts;
@@ -784,7 +769,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
     }
 }
 
-template <typename T, int CAP, bool TWL>
+template <typename T, int CAP>
 __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
 {
     LdsC2<T> *buf = lds_c2<T>();
@@ -799,12 +784,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
     const int nf = it.nf, f0 = it.f0, h = d.h, M = d.M, lbufp = d.lbufp;
     const unsigned npts = (unsigned)a.npts;
     const T *gridb = (const T *)a.in + (uint64_t)f0 * npts + d.grid_off;  // field f at gridb + f npts
-    int buf_off = 0;
-    if (TWL) {
-        for (int k = threadIdx.x; k < d.L; k += kFftThreads) stc(buf + k, W[k]);
-        buf_off = d.L;
-        buf += d.L;
-    }
+    const int buf_off = 0;
 
     // 1. z_k = g_{2k} + i g_{2k+1}; Bluestein: times the chirp, zero-padded to L
     const int span = d.blue ? d.L : h;
@@ -833,7 +813,7 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
         }
     }
     __syncthreads();
-    dft_h<T, CAP, TWL>(buf_off, d, a.passes, nf, W, bhat);
+    dft_h<T, CAP>(buf_off, d, a.passes, nf, W, bhat);
     // 2. split: Y_m = (Z_m + conj Z_{h-m}) / 2 - (i/2) e^{-2 pi i m / n} (Z_m - conj Z_{h-m})
     const T scale = a.adjoint ? T(1) : T(1.0 / d.n);
     C2<T> *fourb = (C2<T> *)a.out + d.four_off + f0;  // (m, f) at fourb[m nfld + f]
@@ -932,7 +912,7 @@ bool check_fft(const Plan &p, int cap)
             if (prod > 1 && (int64_t)cmax * (prod - 1) * pd.tstep >= d.L) SHTX_FFT_FAIL;
             prod *= R;
         }
-        if ((size_t)(d.fb * d.lbufp + extra + (p.fft_tw_lds ? d.L : 0)) * celem > (size_t)p.fft_lds_bytes)
+        if ((size_t)(d.fb * d.lbufp + extra) * celem > (size_t)p.fft_lds_bytes)
             SHTX_FFT_FAIL;
         if (prod != d.L) SHTX_FFT_FAIL;
     }
@@ -953,12 +933,11 @@ hipError_t launch_fft(const Plan &p, const void *in, void *out, bool adjoint, hi
         return hipErrorInvalidValue;
     }
     FftArgs a{p.d_rings, p.d_fft_items, p.d_passes, p.d_twid, in, out, p.nfld, adjoint ? 1 : 0, p.npts};
-    auto kern = C2R ? (p.fft_tw_lds ? k_fft_c2r<T, CAP, true> : k_fft_c2r<T, CAP, false>)
-                    : (p.fft_tw_lds ? k_fft_r2c<T, CAP, true> : k_fft_r2c<T, CAP, false>);
+    auto kern = C2R ? k_fft_c2r<T, CAP> : k_fft_r2c<T, CAP>;
     // raise the kernel's dynamic-LDS limit when a plan needs more than any
     // earlier one (above 64 KiB it must be requested explicitly)
-    static int attr_bytes[2] = {0, 0};
-    int &ab = attr_bytes[p.fft_tw_lds ? 1 : 0];
+    static int attr_bytes = 0;
+    int &ab = attr_bytes;
     if (p.fft_lds_bytes > ab) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, p.fft_lds_bytes);

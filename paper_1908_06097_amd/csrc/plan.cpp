@@ -185,7 +185,7 @@ int fft_blocking(Plan &p, int cap)
     const int F = p.nfld, maxcap = p.prec == SHTX_FP64 ? kFftCapF64 : kFftCapF32;
     const size_t celem = p.prec == SHTX_FP64 ? 16 : 8;
     if (cap < 1 || cap > maxcap) return SHTX_EINVAL;
-    int lds_elems = 0, lds_tw = 0;
+    int lds_elems = 0;
     std::vector<std::vector<FftItem>> fgroups;
     std::vector<double> fcost;
     for (int j = 0; j < p.nlat; ++j) {
@@ -210,15 +210,11 @@ int fft_blocking(Plan &p, int cap)
             d.fb = std::min(d.fb, lim);
         }
         lds_elems = std::max(lds_elems, d.fb * d.lbufp + extra);
-        lds_tw = std::max(lds_tw, d.fb * d.lbufp + extra + d.L);
         std::vector<FftItem> g;
         for (int f0 = 0; f0 < F; f0 += d.fb) g.push_back(FftItem{j, f0, std::min(d.fb, F - f0), 0});
         fgroups.push_back(g);
         fcost.push_back((double)F * d.L * (1 + d.blue) * std::log2((double)d.L + 1));
     }
-    // twiddle tables go to LDS while two blocks still fit one CU's 160 KiB
-    p.fft_tw_lds = (size_t)lds_tw * celem <= 80 * 1024;
-    if (p.fft_tw_lds) lds_elems = lds_tw;
     p.fft_lds_bytes = lds_elems * (int)celem;
     p.fft_lds_max = lds_elems;
     p.fft_cap = cap;

@@ -130,7 +130,6 @@ struct Plan {
     int fft_lds_max = 0;  // complex entries of LDS the largest FFT block may use
     int fft_cap = 0;      // LDS complex values per FFT block the blocking was made for
     int tuned = 0;        // 0 default tiles, 1 timed by the autotuner, 2 from the tune cache
-    bool fft_tw_lds = false;  // FFT blocks stage their twiddle table in LDS
 
     // Device memory.
     double *d_mu = nullptr, *d_w = nullptr;  // nlat
