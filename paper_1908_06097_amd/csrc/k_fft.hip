@@ -497,6 +497,80 @@ __device__ inline void str(unsigned a, T v)
     *(__attribute__((address_space(3))) T *)((LdsByte *)fft_smem + a) = v;
 }
 
+// Geometry of a general prime pass shared by its units (block-uniform values
+// and the lane's position in the 16 x 16 MFMA layout).
+struct GpGeom {
+    int p, H, mt, nb, nbf;
+    unsigned mg_nbf;
+    int buf_off, lbufp, ksteps;
+    unsigned rb, rstr, rspan, rstep, lb;
+    int lr, lk;
+};
+
+// K loop of NJ output units of a general prime pass, run together: for unit
+// (row tile i, column tile g) the lane's matrix operand row is t = 16 i + lr
+// with roots w^{r t}, r = 1 + lk + 4 k, addressed by (r t mod p) rstr and
+// stepped by 4 t mod p with an unsigned min(x, x - span) wrap; its data
+// operand column is c = 16 g + lr = 2 b + (re|im), forming s_r and d_r from
+// x_r and x_{p-r}.  Operands of step k + 1 are read before the products of
+// step k.  Rows r past H in the last step contribute 0.
+template <typename T, int NJ, typename V4>
+__device__ __attribute__((always_inline)) inline void gp_run(const GpGeom &g, const int (&unit)[NJ], V4 *P, V4 *Q,
+                                                             T *x0)
+{
+    constexpr unsigned CB = sizeof(C2<T>), RB = sizeof(T);
+    unsigned ur[NJ], du[NJ], ar[NJ], am[NJ];
+    C2<T> w[NJ];
+    T xr[NJ], xm[NJ];
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        const int i = unit[q] % g.mt, gc = unit[q] / g.mt;
+        const int t = 16 * i + g.lr;
+        ur[q] = (unsigned)((t * (1 + g.lk)) % g.p) * g.rstr;
+        du[q] = (unsigned)((4 * t) % g.p) * g.rstr;
+        const int c = 16 * gc + g.lr;
+        const int b = min(c >> 1, g.nb - 1);
+        const int f = udiv(b, g.mg_nbf), j = b - f * g.nbf;
+        const unsigned slot = g.lb + (unsigned)(g.buf_off + f * g.lbufp + j) * CB + (unsigned)(c & 1) * RB;
+        ar[q] = slot + (unsigned)(1 + g.lk) * g.nbf * CB;
+        am[q] = slot + (unsigned)(g.p - 1 - g.lk) * g.nbf * CB;
+        x0[q] = lda<T>(slot);
+        P[q] = V4{T(0), T(0), T(0), T(0)};
+        Q[q] = V4{T(0), T(0), T(0), T(0)};
+        w[q] = ldc<T>((const LdsC2<T> *)(uintptr_t)(g.rb + ur[q]));
+        xr[q] = lda<T>(ar[q]);
+        xm[q] = lda<T>(am[q]);
+    }
+    for (int k = 0; k < g.ksteps - 1; ++k) {
+        C2<T> w1[NJ];
+        T xr1[NJ], xm1[NJ];
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) {
+            const unsigned nx = ur[q] + du[q];
+            ur[q] = min(nx, nx - g.rspan);
+            ar[q] += g.rstep;
+            am[q] -= g.rstep;
+            w1[q] = ldc<T>((const LdsC2<T> *)(uintptr_t)(g.rb + ur[q]));
+            xr1[q] = lda<T>(ar[q]);
+            xm1[q] = lda<T>(am[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) {
+            P[q] = gp_mfma(w[q].x, xr[q] + xm[q], P[q]);
+            Q[q] = gp_mfma(w[q].y, xr[q] - xm[q], Q[q]);
+            w[q] = w1[q];
+            xr[q] = xr1[q];
+            xm[q] = xm1[q];
+        }
+    }
+    const bool live = 4 * (g.ksteps - 1) + 1 + g.lk <= g.H;
+#pragma unroll
+    for (int q = 0; q < NJ; ++q) {
+        P[q] = gp_mfma(w[q].x, live ? xr[q] + xm[q] : T(0), P[q]);
+        Q[q] = gp_mfma(w[q].y, live ? xr[q] - xm[q] : T(0), Q[q]);
+    }
+}
+
 template <typename T>
 __device__ __attribute__((noinline)) void gp_pass(int buf_off, int lbufp, int nf, PassDesc pd, GlobalC2<T> *Wg)
 {
@@ -519,52 +593,22 @@ __device__ __attribute__((noinline)) void gp_pass(int buf_off, int lbufp, int nf
     const unsigned lb = lds_base(), rb = lb + rbase;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, lr = lane & 15, lk = lane >> 4;
     constexpr int NU = gp_units(sizeof(T) == 8);
+    static_assert(NU % 2 == 0, "units run in pairs");
     V4 accp[NU], accq[NU];
     T x0[NU];
     // 2. units wave, wave + NWV, ...: rows t = 16 i + (0..15), columns
-    //    c = 16 g + (0..15) = 2 b + (re|im)
+    //    c = 16 g + (0..15) = 2 b + (re|im); two units at a time run their
+    //    K loops together (four independent MFMA chains per wave)
+    const GpGeom gm{p, H, mt, nb, nbf, pd.mg_nbf, buf_off, lbufp, ksteps, rb, rstr, rspan, rstep, lb, lr, lk};
 #pragma unroll
-    for (int s = 0; s < NU; ++s) {
-        const int unit = wave + s * NWV;
-        if (unit < nunits) {
-            const int i = unit % mt, g = unit / mt;
-            const int t = 16 * i + lr;  // matrix operand row of this lane
-            // (r t mod p) rstr for r = 1 + lk, stepped by 4 t mod p and wrapped
-            // without a branch: min(x, x - span) in unsigned arithmetic
-            unsigned ur = (unsigned)((t * (1 + lk)) % p) * rstr;
-            const unsigned du = (unsigned)((4 * t) % p) * rstr;
-            const int c = 16 * g + lr;  // data operand column of this lane
-            const int b = min(c >> 1, nb - 1);
-            const int f = udiv(b, pd.mg_nbf), j = b - f * nbf;
-            const unsigned slot = (unsigned)(buf_off + f * lbufp + j) * CB + (unsigned)(c & 1) * RB;
-            // absolute addresses of x_r and x_{p-r}, stepped by 4 rows
-            unsigned ar = lb + slot + (unsigned)(1 + lk) * nbf * CB, am = lb + slot + (unsigned)(p - 1 - lk) * nbf * CB;
-            V4 P = {T(0), T(0), T(0), T(0)}, Q = {T(0), T(0), T(0), T(0)};
-            // operands of step k + 1 are read before the products of step k
-            C2<T> w = ldc<T>((const LdsC2<T> *)(uintptr_t)(rb + ur));
-            T xr = lda<T>(ar), xm = lda<T>(am);
-            for (int k = 0; k < ksteps - 1; ++k) {
-                const unsigned nx = ur + du;
-                ur = min(nx, nx - rspan);
-                ar += rstep;
-                am -= rstep;
-                const C2<T> w1 = ldc<T>((const LdsC2<T> *)(uintptr_t)(rb + ur));
-                const T xr1 = lda<T>(ar), xm1 = lda<T>(am);
-                P = gp_mfma(w.x, xr + xm, P);
-                Q = gp_mfma(w.y, xr - xm, Q);
-                w = w1;
-                xr = xr1;
-                xm = xm1;
-            }
-            {
-                // last step: rows r = 4 (ksteps - 1) + 1 + lk past H contribute 0
-                const bool live = 4 * (ksteps - 1) + 1 + lk <= H;
-                P = gp_mfma(w.x, live ? xr + xm : T(0), P);
-                Q = gp_mfma(w.y, live ? xr - xm : T(0), Q);
-            }
-            accp[s] = P;
-            accq[s] = Q;
-            x0[s] = ldr<T>(slot);
+    for (int s = 0; s < NU; s += 2) {
+        const int ua = wave + s * NWV, ub = wave + (s + 1) * NWV;
+        if (ub < nunits) {
+            const int u2[2] = {ua, ub};
+            gp_run<T, 2>(gm, u2, accp + s, accq + s, x0 + s);
+        } else if (ua < nunits) {
+            const int u1[1] = {ua};
+            gp_run<T, 1>(gm, u1, accp + s, accq + s, x0 + s);
         }
     }
     __syncthreads();
