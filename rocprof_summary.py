@@ -13,6 +13,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import statistics
 import sys
 
@@ -28,8 +29,15 @@ COPY_BYTES = 1 << 30
 
 def classify(name):
     if "k_leg_mfma" in name or "k_leg_bf16x3" in name:
-        # the inverse-shaped instantiation has template argument `true`
-        inv = ("true>" in name) or ("Lb1E" in name)
+        # the inverse-shaped instantiation has template argument INV = true
+        # (5th of k_leg_mfma<T, BM, BN, BK, INV, NW>, 4th of k_leg_bf16x3)
+        args = re.search(r"<([^<>]*)>", name)
+        if args:
+            parts = [x.strip() for x in args.group(1).split(",")]
+            pos = 4 if "k_leg_mfma" in name else 3
+            inv = len(parts) > pos and parts[pos] == "true"
+        else:
+            inv = "Lb1E" in name
         return "legendre_inverse_gemm" if inv else "legendre_direct_gemm"
     if "k_fft_c2r" in name:
         return "ring_fft_c2r"
@@ -51,13 +59,18 @@ def main():
     trace, fetch, write, workload, prec = sys.argv[1:6]
     command = " ".join(sys.argv[6:])
     stats = list(csv.DictReader(open(one(os.path.join(trace, "**", "*kernel_stats.csv")))))
+    # a stage may be more than one kernel (a GEMM's main and column-tail
+    # launches, one each per stage call): its time per call is the sum of
+    # its kernels' averages
     dur = {}
     for r in stats:
         k = classify(r["Name"])
         if k and k != "copy":
-            dur[k] = (float(r["AverageNs"]) / 1e6, int(r["Calls"]), r["Name"])
+            ms, calls, names = dur.get(k, (0.0, 0, []))
+            dur[k] = (ms + float(r["AverageNs"]) / 1e6, max(calls, int(r["Calls"])), names + [r["Name"]])
 
     def counter(d, cname):
+        """Per stage: the sum over its kernels of each kernel's mean per dispatch."""
         rows = list(csv.DictReader(open(one(os.path.join(d, "**", "*counter_collection.csv")))))
         per = {}
         for r in rows:
@@ -67,8 +80,10 @@ def main():
             if k == "copy" and float(r["Counter_Value"]) * 1024 < COPY_BYTES / 2:
                 continue  # the fill kernels of the calibration tensors, not the copy
             if k:
-                per.setdefault(k, []).append(float(r["Counter_Value"]))
-        return per
+                per.setdefault(k, {}).setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        out = {k: [sum(statistics.mean(v) for v in by_name.values())] for k, by_name in per.items() if k != "copy"}
+        out["copy"] = [x for v in per.get("copy", {}).values() for x in v]  # calibration: largest single copy
+        return out
 
     fr, wr = counter(fetch, "FETCH_SIZE"), counter(write, "WRITE_SIZE")
     f_scale = COPY_BYTES / (max(fr["copy"]) * 1024)
@@ -87,8 +102,9 @@ def main():
         tag = workload.lower().replace(" ", "_")
         with open(os.path.join(ROOT, "profiles", f"{k}_{tag}_{prec}.md"), "w") as fh:
             fh.write(f"# {k} — {workload}, {prec}\n\n")
-            fh.write(f"Kernel: `{dur[k][2]}`\n\n")
-            fh.write(f"* rocprofv3 kernel trace: {dur[k][1]} launches, average {dur[k][0]:.3f} ms\n")
+            fh.write("Kernels: " + ", ".join(f"`{n}`" for n in dur[k][2]) + "\n\n")
+            fh.write(f"* rocprofv3 kernel trace: {dur[k][1]} stage calls, average {dur[k][0]:.3f} ms per call"
+                     f"{' (sum of its kernels)' if len(dur[k][2]) > 1 else ''}\n")
             fh.write(f"* FETCH_SIZE per launch: {fb / 1e9:.3f} GB (raw x {f_scale:.3f}, scale from a 1 GiB copy)\n")
             fh.write(f"* WRITE_SIZE per launch: {wb / 1e9:.3f} GB (raw x {w_scale:.3f})\n")
             fh.write(f"* HBM traffic per launch: {(fb + wb) / 1e9:.3f} GB -> {(fb + wb) / (dur[k][0] * 1e-3) / 1e9:.0f} GB/s\n\n")
