@@ -134,13 +134,17 @@ def roofline_for(res, prec):
 def traffic_for(kernel, workload, prec):
     """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by
     a copy kernel of known size) from the committed counter summary, only if
-    the kernel's source file is unchanged since the counters were taken."""
+    no library source (kernels, headers, planning code) has changed since the
+    counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
         if rec.get("workload") != workload or rec.get("prec") != prec:
+            return None
+        from paper_1908_06097_amd.build import build_id
+        if rec.get("library_build_id") != build_id():
             return None
         k = rec["kernels"][kernel]
         src = open(os.path.join(ROOT, "paper_1908_06097_amd", "csrc", k["source"]), "rb").read()

@@ -17,8 +17,8 @@ namespace shtx {
 constexpr int kTablePad = 128;
 
 // Ring-FFT kernels hold at most this many complex values of one block in LDS.
-constexpr int kFftCapF32 = 6144;  // 48 KiB before padding
-constexpr int kFftCapF64 = 6144;  // 96 KiB
+constexpr int kFftCapF32 = 8192;  // 64 KiB: two blocks per CU with the prime-pass roots
+constexpr int kFftCapF64 = 8192;  // 128 KiB: one block per CU (the FP64 passes use 228 VGPRs)
 constexpr int kFftThreads = 512;
 
 // Butterflies per thread in a radix-R Stockham pass (rounds of kFftThreads):

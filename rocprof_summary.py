@@ -6,7 +6,8 @@ Usage (after the three runs listed in profiles/README.md):
 Writes profiles/<kernel>_<workload>_<prec>.md (average duration per kernel
 from the kernel trace, and HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by
 the 1 GiB calibration copy) and profiles/traffic.json (bytes per launch per
-kernel with the sha256 of the source file the kernel was built from).
+kernel with the sha256 of the source file the kernel was built from, and the
+hash of every library source).
 """
 import csv
 import glob
@@ -88,7 +89,9 @@ def main():
     fr, wr = counter(fetch, "FETCH_SIZE"), counter(write, "WRITE_SIZE")
     f_scale = COPY_BYTES / (max(fr["copy"]) * 1024)
     w_scale = COPY_BYTES / (max(wr["copy"]) * 1024)
-    out = {"workload": workload, "prec": prec, "command": command,
+    sys.path.insert(0, ROOT)
+    from paper_1908_06097_amd.build import build_id
+    out = {"workload": workload, "prec": prec, "command": command, "library_build_id": build_id(),
            "copy_calibration": {"fetch_scale": f_scale, "write_scale": w_scale}, "kernels": {}}
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     for k, (_, src) in KERNELS.items():

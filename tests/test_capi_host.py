@@ -8,6 +8,10 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
+# Largest LDS complex values per FFT block (single-precision FFTs also serve
+# BF16x3) and the autotuner's other two blockings.
+FFT_CAPS = {"fp32": (8192, 4096, 2730), "bf16x3": (8192, 4096, 2730), "fp64": (8192, 4096, 2730)}
+
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "shtx.h")).read()
@@ -103,7 +107,8 @@ def test_plan_check_every_tuning_shape(lib, prec, shapes):
     for key in ("t255_o256", "t399_o400"):
         w = si.WORKLOADS[key]
         for t in shapes:
-            for cap in (6144, 3072, 2048):
+            # the autotuner's FFT blockings: the precision's LDS cap, 1/2 and 1/3 of it
+            for cap in FFT_CAPS[prec]:
                 rc, info = shtx.plan_check_shapes(w.trunc, w.grid, w.nlat, w.nfld, prec, t, t, cap, w.nlon_full)
                 assert rc == 0, (key, prec, t, cap, rc)
                 assert tuple(info.inv_tile) == t and tuple(info.dir_tile) == t and info.fft_cap == cap
@@ -115,4 +120,5 @@ def test_plan_check_shapes_rejects(lib):
     assert shtx.plan_check_shapes(255, "octahedral", 512, 7, "fp32", (64, 64), (128, 128), 6144)[0] == -4
     assert shtx.plan_check_shapes(255, "octahedral", 512, 7, "fp64", (128, 128), (64, 64), 6144)[0] == -4
     assert shtx.plan_check_shapes(255, "octahedral", 512, 7, "fp32", (128, 128), (128, 128), 0)[0] == -1
-    assert shtx.plan_check_shapes(255, "octahedral", 512, 7, "fp32", (128, 128), (128, 128), 6145)[0] == -1
+    assert shtx.plan_check_shapes(255, "octahedral", 512, 7, "fp32", (128, 128), (128, 128), FFT_CAPS["fp32"][0] + 1)[0] == -1
+    assert shtx.plan_check_shapes(255, "octahedral", 512, 7, "fp64", (64, 64), (64, 64), FFT_CAPS["fp64"][0] + 1)[0] == -1
