@@ -4,7 +4,7 @@ Usage (after the three runs listed in profiles/README.md):
     python rocprof_summary.py <trace_dir> <fetch_dir> <write_dir> <workload> <prec> <command...>
 
 Writes profiles/<kernel>_<workload>_<prec>.md (average duration per kernel
-from the kernel trace, and HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by
+from the kernel trace, without each kernel's first (warm-up) dispatch, and HBM bytes from FETCH_SIZE / WRITE_SIZE scaled by
 the 1 GiB calibration copy) and profiles/traffic.json (bytes per launch per
 kernel with the sha256 of the source file the kernel was built from, and the
 hash of every library source).
@@ -59,16 +59,24 @@ def one(pattern):
 def main():
     trace, fetch, write, workload, prec = sys.argv[1:6]
     command = " ".join(sys.argv[6:])
-    stats = list(csv.DictReader(open(one(os.path.join(trace, "**", "*kernel_stats.csv")))))
-    # a stage may be more than one kernel (a GEMM's main and column-tail
-    # launches, one each per stage call): its time per call is the sum of
-    # its kernels' averages
-    dur = {}
-    for r in stats:
-        k = classify(r["Name"])
+    # per kernel, dispatch durations from the kernel trace in launch order; the
+    # first dispatch of each kernel is the bench's untimed warm-up call and is
+    # left out.  A stage may be more than one kernel (a GEMM's main and
+    # column-tail launches, one each per stage call): its time per call is the
+    # sum of its kernels' averages.
+    rows = list(csv.DictReader(open(one(os.path.join(trace, "**", "*kernel_trace.csv")))))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    per_name = {}
+    for r in rows:
+        k = classify(r["Kernel_Name"])
         if k and k != "copy":
-            ms, calls, names = dur.get(k, (0.0, 0, []))
-            dur[k] = (ms + float(r["AverageNs"]) / 1e6, max(calls, int(r["Calls"])), names + [r["Name"]])
+            d_ms = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+            per_name.setdefault(k, {}).setdefault(r["Kernel_Name"], []).append(d_ms)
+    dur = {}
+    for k, by_name in per_name.items():
+        ms = sum(statistics.mean(v[1:] if len(v) > 1 else v) for v in by_name.values())
+        calls = max(max(len(v) - 1, 1) for v in by_name.values())
+        dur[k] = (ms, calls, list(by_name))
 
     def counter(d, cname):
         """Per stage: the sum over its kernels of each kernel's mean per dispatch."""
@@ -106,8 +114,8 @@ def main():
         with open(os.path.join(ROOT, "profiles", f"{k}_{tag}_{prec}.md"), "w") as fh:
             fh.write(f"# {k} — {workload}, {prec}\n\n")
             fh.write("Kernels: " + ", ".join(f"`{n}`" for n in dur[k][2]) + "\n\n")
-            fh.write(f"* rocprofv3 kernel trace: {dur[k][1]} stage calls, average {dur[k][0]:.3f} ms per call"
-                     f"{' (sum of its kernels)' if len(dur[k][2]) > 1 else ''}\n")
+            fh.write(f"* rocprofv3 kernel trace: {dur[k][1]} timed stage calls (warm-up call left out), average "
+                     f"{dur[k][0]:.3f} ms per call{' (sum of its kernels)' if len(dur[k][2]) > 1 else ''}\n")
             fh.write(f"* FETCH_SIZE per launch: {fb / 1e9:.3f} GB (raw x {f_scale:.3f}, scale from a 1 GiB copy)\n")
             fh.write(f"* WRITE_SIZE per launch: {wb / 1e9:.3f} GB (raw x {w_scale:.3f})\n")
             fh.write(f"* HBM traffic per launch: {(fb + wb) / 1e9:.3f} GB -> {(fb + wb) / (dur[k][0] * 1e-3) / 1e9:.0f} GB/s\n\n")

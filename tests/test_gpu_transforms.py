@@ -132,6 +132,33 @@ def test_transform_parity(prec, shape):
     _check_all(plan, N, nlon, 11, range(F), prec)
 
 
+# Full grids of one ring length each, one per kind of ring FFT plan: half
+# lengths h = 2 p with a prime p above 191 (single precision runs these as a
+# matrix-core prime pass up to the cost model's crossover, double precision
+# through Bluestein), a prime above the crossover, two large primes, and a
+# small prime with a large smooth cofactor.
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("nlon", [844, 1604, 2452, 3596, 4084, 5180])
+def test_ring_kinds_parity(prec, nlon):
+    shtx = _shtx()
+    N, nlat, F = 31, 16, 3
+    _say(f"ring kinds nlon={nlon} {prec}")
+    plan = shtx.Plan(N, "full", nlat, F, prec, nlon_full=nlon)
+    _check_all(plan, N, plan.ring_lengths(), 13, range(F), prec)
+
+
+# Legendre GEMM column tiling: 128 columns exactly (64 fields), a last tile at
+# most half used (70 fields: covered by the 64-column tail launch) and one
+# more than half used (100 fields: no tail).
+@pytest.mark.parametrize("F", [64, 70, 100])
+def test_gemm_column_tiles_fp32(F):
+    shtx = _shtx()
+    N, nlat = 63, 128
+    _say(f"column tiles F={F}")
+    plan = shtx.Plan(N, "octahedral", nlat, F, "fp32")
+    _check_all(plan, N, plan.ring_lengths(), 17, range(F), "fp32")
+
+
 def test_t79_full_fp64_round_trip():
     """T79 on the full 160 x 320 grid, 1 field, FP64: parity and round trip <= 1e-12."""
     shtx, o = _shtx(), _oracle()
