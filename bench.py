@@ -39,7 +39,9 @@ def parse():
                     help="extra precision forms timed beside the headline (comma list, or none)")
     ap.add_argument("--form-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-fields", type=int, default=1)
+    ap.add_argument("--cpu-fields", type=int, default=0,
+                    help="fields the oracle baseline transforms (0: as many as take about 15 s, "
+                         "at most the workload's field count)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the fixed default tile shapes instead of the plan-time autotuner")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -155,17 +157,30 @@ def traffic_for(kernel, workload, prec):
         return None
 
 
-def cpu_baseline(wl, nfields, spec_np):
+def cpu_baseline(wl, nfields, spec_np, target_s=15.0):
+    """The oracle (inverse then direct) on a bounded sample of the workload's
+    fields: `nfields` of them, or, if 0, one field and then as many more as
+    bring the sample to about `target_s` seconds."""
+    import numpy as np
     import oracle
     nlon = wl.ring_lengths()
-    a = spec_np[:nfields]
     t0 = time.perf_counter()
-    g = oracle.inv(wl.trunc, nlon, a)
+    n = max(nfields, 1)
+    g = oracle.inv(wl.trunc, nlon, spec_np[:n])
     b = oracle.dir(wl.trunc, nlon, g)
     dt = time.perf_counter() - t0
-    return {"value": nfields / dt, "unit": "fields/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"inv+dir of {nfields} of the {wl.nfld} fields of {wl.name} (per-field cost is identical)",
-            "seconds": dt}, g, b
+    if nfields == 0:
+        more = min(wl.nfld, max(1, int(round(target_s / max(dt, 1e-6))))) - 1
+        if more > 0:
+            t1 = time.perf_counter()
+            g2 = oracle.inv(wl.trunc, nlon, spec_np[1:1 + more])
+            b2 = oracle.dir(wl.trunc, nlon, g2)
+            dt += time.perf_counter() - t1
+            g, b = np.concatenate([g, g2]), np.concatenate([b, b2])
+            n += more
+    return {"value": n / dt, "unit": "fields/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"inv+dir of {n} of the {wl.nfld} fields of {wl.name} (per-field cost is identical)",
+            "seconds": dt}, g, b, n
 
 
 def errors_vs_oracle(torch, res, g_ref, b_ref, wl, nfields):
@@ -237,10 +252,11 @@ def main():
         "plan_seconds": float(res["plan"].info.plan_seconds),
     }
     if not args.no_cpu_baseline:
-        print(f"[bench] cpu baseline: oracle on {args.cpu_fields} field(s)", file=sys.stderr, flush=True)
-        cb, g_ref, b_ref = cpu_baseline(wl, args.cpu_fields, spec_np)
+        print(f"[bench] cpu baseline: oracle on {args.cpu_fields or 'about 15 s of'} field(s)", file=sys.stderr,
+              flush=True)
+        cb, g_ref, b_ref, n_ref = cpu_baseline(wl, args.cpu_fields, spec_np)
         line["cpu_baseline"] = cb
-        line["error_vs_oracle"] = errors_vs_oracle(torch, res, g_ref, b_ref, wl, args.cpu_fields)
+        line["error_vs_oracle"] = errors_vs_oracle(torch, res, g_ref, b_ref, wl, n_ref)
     res["plan"].close()
     del res
     torch.cuda.empty_cache()
@@ -254,7 +270,7 @@ def main():
                        "kernel_ms": r["kernel_ms"], "tiles": tiles_of(r["plan"]),
                        "legendre_frac": {k: rf[k]["frac"] for k in rf if k.startswith("legendre")}}
         if not args.no_cpu_baseline:
-            forms[prec]["error_vs_oracle"] = errors_vs_oracle(torch, r, g_ref, b_ref, wl, args.cpu_fields)
+            forms[prec]["error_vs_oracle"] = errors_vs_oracle(torch, r, g_ref, b_ref, wl, n_ref)
         r["plan"].close()
         del r
         torch.cuda.empty_cache()
