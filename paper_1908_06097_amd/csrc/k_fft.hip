@@ -752,13 +752,15 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
             // 32-bit unsigned element offsets from the block's base pointers
             if (ok && m <= M) ym[u] = fourb[(unsigned)m * nfld + (unsigned)f];
             if (ok && h - m <= M) yh[u] = fourb[(unsigned)(h - m) * nfld + (unsigned)f];
+            // e^{-2 pi i (h - m) / n} = -conj(e^{-2 pi i m / n}); the chirp at h - m
+            // is the chirp at m times (-1)^h (m > 0)
             pm[u] = post[(unsigned)m];
-            ph[u] = post[(unsigned)(h - m)];
+            ph[u] = C2<T>{-pm[u].x, pm[u].y};
             cm[u] = zero;
             ch[u] = zero;
             if (d.blue) {
                 cm[u] = chirp[(unsigned)m];
-                ch[u] = chirp[(unsigned)(m == 0 ? 0 : h - m)];
+                ch[u] = (m > 0 && (h & 1)) ? C2<T>{-cm[u].x, -cm[u].y} : cm[u];
             }
         }
 #pragma unroll
@@ -874,8 +876,9 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
             cm[u] = C2<T>{T(1), T(0)};
             ch[u] = C2<T>{T(1), T(0)};
             if (d.blue) {
+                // the chirp at h - m is the chirp at m times (-1)^h (m > 0)
                 cm[u] = chirp[(unsigned)m];
-                ch[u] = chirp[(unsigned)(m == 0 ? 0 : h - m)];
+                ch[u] = (m > 0 && (h & 1)) ? C2<T>{-cm[u].x, -cm[u].y} : cm[u];
             }
         }
 #pragma unroll
