@@ -702,6 +702,15 @@ __device__ void dft_h(int buf_off, const RingDesc &d, const PassDesc *passes, in
 }
 
 
+// A ring's grid rows can be moved two complex values (four points) at a time
+// with 16-byte accesses: no chirp, even h, and every field's row of the ring
+// starting on a 16-byte boundary (the block's first row aligned, field stride
+// a multiple of 4 points).
+__device__ inline bool grid_pairs(const RingDesc &d, int h, unsigned npts, const void *row0)
+{
+    return !d.blue && (h & 1) == 0 && (npts & 3u) == 0 && (reinterpret_cast<uintptr_t>(row0) & 15) == 0;
+}
+
 template <typename T, int CAP>
 __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
 {
@@ -793,6 +802,25 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_c2r(FftArgs a)
     const T scale = a.adjoint ? T(d.w / (2.0 * d.n)) : T(1);
     const unsigned npts = (unsigned)a.npts;
     T *gridb = (T *)a.out + (uint64_t)f0 * npts + d.grid_off;  // field f at gridb + f npts
+    // single precision, no chirp, even h and 16-byte aligned rows: two complex
+    // values (four grid points) per element with one 16-byte store
+    if (sizeof(T) == 4 && grid_pairs(d, h, npts, gridb)) {
+        typedef T V4 __attribute__((ext_vector_type(4)));
+        const int hh = h / 2;
+        const unsigned mg_hh = div_magic(hh);
+        for (int e0 = threadIdx.x; e0 < nf * hh; e0 += kU * kFftThreads) {
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int e = e0 + u * kFftThreads;
+                if (e >= nf * hh) continue;
+                const int f = udiv(e, mg_hh), kk = e - f * hh;
+                const C2<T> x0 = ldc(buf + f * lbufp + 2 * kk), x1 = ldc(buf + f * lbufp + 2 * kk + 1);
+                *reinterpret_cast<V4 *>(gridb + (uint64_t)(unsigned)f * npts + 4u * (unsigned)kk) =
+                    V4{scale * x0.x, -scale * x0.y, scale * x1.x, -scale * x1.y};
+            }
+        }
+        return;
+    }
     const unsigned mg_h = div_magic(h);
     for (int e0 = threadIdx.x; e0 < nf * h; e0 += kU * kFftThreads) {
         C2<T> cp[kU];
@@ -835,7 +863,34 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
     // 1. z_k = g_{2k} + i g_{2k+1}; Bluestein: times the chirp, zero-padded to L
     const int span = d.blue ? d.L : h;
     const unsigned mg_span = div_magic(span);
-    for (int e0 = threadIdx.x; e0 < nf * span; e0 += kU * kFftThreads) {
+    // single precision, no chirp, even h and 16-byte aligned rows: four grid
+    // points (two complex values) per element with one 16-byte load
+    const bool pairs = sizeof(T) == 4 && grid_pairs(d, h, npts, gridb);
+    if (pairs) {
+        typedef T V4 __attribute__((ext_vector_type(4)));
+        const int hh = h / 2;
+        const unsigned mg_hh = div_magic(hh);
+        for (int e0 = threadIdx.x; e0 < nf * hh; e0 += kU * kFftThreads) {
+            V4 gv[kU];
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int e = e0 + u * kFftThreads;
+                if (e < nf * hh) {
+                    const int f = udiv(e, mg_hh), kk = e - f * hh;
+                    gv[u] = *reinterpret_cast<const V4 *>(gridb + (uint64_t)(unsigned)f * npts + 4u * (unsigned)kk);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int e = e0 + u * kFftThreads;
+                if (e >= nf * hh) continue;
+                const int f = udiv(e, mg_hh), kk = e - f * hh;
+                stc(buf + f * lbufp + 2 * kk, C2<T>{gv[u].x, gv[u].y});
+                stc(buf + f * lbufp + 2 * kk + 1, C2<T>{gv[u].z, gv[u].w});
+            }
+        }
+    }
+    for (int e0 = pairs ? nf * span : threadIdx.x; e0 < nf * span; e0 += kU * kFftThreads) {
         C2<T> z[kU], cp[kU];
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
