@@ -478,11 +478,6 @@ __device__ inline gp_f64x4 gp_mfma(double a, double b, gp_f64x4 c)
 {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
-template <typename T>
-__device__ inline T ldr(unsigned a)
-{
-    return *(const __attribute__((address_space(3))) T *)((LdsByte *)fft_smem + a);
-}
 // Absolute LDS addresses (the dynamic LDS base already added), for loops that
 // step addresses instead of re-adding the base at every access.
 __device__ inline unsigned lds_base() { return (unsigned)(uintptr_t)(LdsByte *)fft_smem; }
@@ -491,6 +486,7 @@ __device__ inline T lda(unsigned a)
 {
     return *(const __attribute__((address_space(3))) T *)(uintptr_t)a;
 }
+// One real value to LDS at byte offset a of the dynamic LDS.
 template <typename T>
 __device__ inline void str(unsigned a, T v)
 {
@@ -592,7 +588,7 @@ __device__ __attribute__((noinline)) void gp_pass(int buf_off, int lbufp, int nf
     const unsigned rspan = (unsigned)p * rstr, rstep = 4u * nbf * CB;
     const unsigned lb = lds_base(), rb = lb + rbase;
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64, lr = lane & 15, lk = lane >> 4;
-    constexpr int NU = gp_units(sizeof(T) == 8);
+    constexpr int NU = kGpUnits;
     static_assert(NU % 2 == 0, "units run in pairs");
     V4 accp[NU], accq[NU];
     T x0[NU];
@@ -989,12 +985,12 @@ bool check_fft(const Plan &p, int cap)
             if (R < 2 || d.L % R) SHTX_FFT_FAIL;
             if (is_gp_radix<T>(R)) {
                 // a general prime pass: the first pass only, an odd prime up to
-                // gp_max_prime, at most gp_units output units per wave
+                // gp_max_prime, at most kGpUnits output units per wave
                 if (s != 0 || code != 0 || R > gp_max_prime(sizeof(T) == 8) || R % 2 == 0 || d.blue) SHTX_FFT_FAIL;
                 for (int q = 3; q * q <= R; q += 2)
                     if (R % q == 0) SHTX_FFT_FAIL;
                 if ((int64_t)gp_row_tiles(R) * gp_col_tiles(d.fb * pd.nbf) >
-                    (int64_t)gp_units(sizeof(T) == 8) * (kFftThreads / 64))
+                    (int64_t)kGpUnits * (kFftThreads / 64))
                     SHTX_FFT_FAIL;
                 extra = R;
             } else {

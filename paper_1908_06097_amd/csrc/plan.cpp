@@ -193,7 +193,7 @@ int fft_blocking(Plan &p, int cap)
         if (d.lbuf > maxcap) return SHTX_EUNSUPPORTED;
         d.fb = std::max(1, std::min(F, cap / d.lbuf));
         // passes of radix 11 and up run one round of kFftThreads butterflies;
-        // a general prime pass holds at most gp_units output units per wave
+        // a general prime pass holds at most kGpUnits output units per wave
         int extra = 0;
         for (int s = 0; s < d.nrad; ++s) {
             const PassDesc &q = p.passes[d.pass_off + s];
@@ -201,7 +201,7 @@ int fft_blocking(Plan &p, int cap)
             int lim;
             if (R > 23 || (p.prec == SHTX_FP64 && R > 17)) {
                 // units = row tiles x ceil(2 fb nbf / 16)
-                lim = 8 * (gp_units(p.prec == SHTX_FP64) * (kFftThreads / 64) / gp_row_tiles(R)) / q.nbf;
+                lim = 8 * (kGpUnits * (kFftThreads / 64) / gp_row_tiles(R)) / q.nbf;
                 extra = R;
             } else {
                 lim = fft_rounds(maxcap, R) * kFftThreads / q.nbf;
@@ -393,7 +393,7 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         // FFT timings on MI355X, in ps per grid point: prime pass
         // 3.2 + 0.0086 p, Bluestein 0.37 (L / h) log2 L) favours it
         bool gp = rem > 1 && rem <= gp_max_prime(dbl) && is_prime(rem) &&
-                  gp_row_tiles(rem) * gp_col_tiles(h / rem) <= gp_units(dbl) * (kFftThreads / 64);
+                  gp_row_tiles(rem) * gp_col_tiles(h / rem) <= kGpUnits * (kFftThreads / 64);
         if (gp && rem > 191) gp = 3.2 + 0.0086 * rem < 0.37 * Lb / h * std::log2((double)Lb);
         if (rem == 1 || gp) {
             lp.L = h;
