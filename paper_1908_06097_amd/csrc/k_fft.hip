@@ -985,8 +985,8 @@ bool check_fft(const Plan &p, int cap)
             if (R < 2 || d.L % R) SHTX_FFT_FAIL;
             if (is_gp_radix<T>(R)) {
                 // a general prime pass: the first pass only, an odd prime up to
-                // gp_max_prime, at most kGpUnits output units per wave
-                if (s != 0 || code != 0 || R > gp_max_prime(sizeof(T) == 8) || R % 2 == 0 || d.blue) SHTX_FFT_FAIL;
+                // kGpMaxPrime, at most kGpUnits output units per wave
+                if (s != 0 || code != 0 || R > kGpMaxPrime || R % 2 == 0 || d.blue) SHTX_FFT_FAIL;
                 for (int q = 3; q * q <= R; q += 2)
                     if (R % q == 0) SHTX_FFT_FAIL;
                 if ((int64_t)gp_row_tiles(R) * gp_col_tiles(d.fb * pd.nbf) >

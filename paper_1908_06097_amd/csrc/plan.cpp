@@ -386,13 +386,15 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
             return x == 1 && threes >= 2;
         };
         while (!ok23(Lb)) ++Lb;
-        // one prime factor above the register radices, up to gp_max_prime, is
+        // one prime factor above the register radices, up to kGpMaxPrime, is
         // run as a general prime pass (first, at Ns = 1) instead of Bluestein
         // when one field's output units fit the block's waves and, above 191,
         // when the cost model of the two (fitted to single-precision ring
         // FFT timings on MI355X, in ps per grid point: prime pass
-        // 3.2 + 0.0086 p, Bluestein 0.37 (L / h) log2 L) favours it
-        bool gp = rem > 1 && rem <= gp_max_prime(dbl) && is_prime(rem) &&
+        // 3.2 + 0.0086 p, Bluestein 0.37 (L / h) log2 L) favours it; the same
+        // choice measured faster in double precision too (C5 c2r 29.2 ->
+        // 27.1 ms against the prime pass limited to 191)
+        bool gp = rem > 1 && rem <= kGpMaxPrime && is_prime(rem) &&
                   gp_row_tiles(rem) * gp_col_tiles(h / rem) <= kGpUnits * (kFftThreads / 64);
         if (gp && rem > 191) gp = 3.2 + 0.0086 * rem < 0.37 * Lb / h * std::log2((double)Lb);
         if (rem == 1 || gp) {

@@ -31,13 +31,13 @@ __host__ __device__ constexpr int fft_rounds(int cap, int R)
 }
 
 // General prime pass: a ring whose half-length has one prime factor p above
-// the register radices, p <= gp_max_prime, runs it as the first pass on the
+// the register radices, p <= kGpMaxPrime, runs it as the first pass on the
 // matrix cores, reading the p-th roots of unity from p LDS entries after the
 // field slots.  Its outputs come in units of 16 rows t (t = 0 .. (p-1)/2) by
 // 16 columns (butterfly, real | imaginary part); each wave holds at most
 // kGpUnits units (more would push the single-precision FFT kernels past the
 // 128 VGPRs that keep two blocks per CU).
-__host__ __device__ constexpr int gp_max_prime(bool dbl) { return dbl ? 191 : 1021; }
+constexpr int kGpMaxPrime = 1021;
 constexpr int kGpUnits = 4;
 __host__ __device__ constexpr int gp_row_tiles(int p) { return ((p - 1) / 2 + 16) / 16; }
 __host__ __device__ constexpr int gp_col_tiles(int nbutterflies) { return (2 * nbutterflies + 15) / 16; }

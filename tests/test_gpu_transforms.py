@@ -133,12 +133,11 @@ def test_transform_parity(prec, shape):
 
 
 # Full grids of one ring length each, one per kind of ring FFT plan: half
-# lengths h = 2 p with a prime p above 191 (single precision runs these as a
-# matrix-core prime pass up to the cost model's crossover, double precision
-# through Bluestein), a prime above the crossover, two large primes, a small
-# prime with a large smooth cofactor, and odd half lengths (h = 211, a single
-# prime butterfly; h = 1021, Bluestein in both precisions), where the chirp
-# at h - m is minus the chirp at m.
+# lengths h = 2 p with a prime p above 191 (a matrix-core prime pass up to the
+# cost model's crossover), a prime above the crossover (Bluestein), two large
+# primes, a small prime with a large smooth cofactor, and odd half lengths
+# (h = 211, a single prime butterfly; h = 1021, Bluestein), where the chirp at
+# h - m is minus the chirp at m.
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("nlon", [844, 1604, 2452, 3596, 4084, 5180, 422, 2042])
 def test_ring_kinds_parity(prec, nlon):
