@@ -5,14 +5,26 @@ transform (Legendre GEMM + ring c2r FFT) of every field, then the direct
 transform (ring r2c FFT + Legendre GEMM) of the resulting grids.  Inputs are
 resident in HBM before the timed region.  The default workload is TCo1279 on
 O1280 with 411 fields and FP32 Legendre GEMMs; the same step is also timed in
-FP64-plain and split-BF16 forms and reported beside it.
+the FP64-plain and split-precision forms and reported beside it.
 
-Prints one JSON line (see the design doc for every field's definition).
+Each form is measured in two passes over one plan:
+  1. the product path: each transform replayed as its captured hipGraph on a
+     non-default stream, HIP events around every step; `value` is fields per
+     second at the median step time (the minimum and the wall-clock rate are
+     reported too);
+  2. the kernel breakdown: the same steps launched eagerly with the library's
+     per-kernel HIP events on the launch stream; these average durations give
+     the roofline figures.
+The forward + adjoint pair (inverse transform, then the adjoint of the
+inverse applied to its grids) is timed the same way as pass 1.
+
+Prints one JSON line (the design doc defines every field).
 """
 import argparse
 import hashlib
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -24,21 +36,29 @@ PEAK = {  # MI355X published dense peaks
     "fp64_TF": 78.6,
     "fp32_TF": 157.3,
     "bf16_TF": 2500.0,
+    "fp16_TF": 2500.0,
 }
+PEAK_TF = {"fp64": PEAK["fp64_TF"], "fp32": PEAK["fp32_TF"], "bf16x3": PEAK["bf16_TF"], "fp16x3": PEAK["fp16_TF"]}
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3", "fp16x3": "fp16x3"}
 KERNELS = ["legendre_inverse_gemm", "legendre_direct_gemm", "ring_fft_c2r", "ring_fft_r2c"]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="tco1279_o1280")
-    ap.add_argument("--prec", default="fp32", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--prec", default="fp32", choices=sorted(PEAK_TF))
     ap.add_argument("--forms", default="fp64,bf16x3",
                     help="extra precision forms timed beside the headline (comma list, or none)")
-    ap.add_argument("--form-steps", type=int, default=3)
+    ap.add_argument("--form-steps", type=int, default=5)
+    ap.add_argument("--kernel-steps", type=int, default=5,
+                    help="eager steps with per-kernel events (the roofline figures)")
+    ap.add_argument("--no-pair", action="store_true", help="skip the inverse + adjoint-of-inverse pair")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-single-core", action="store_true",
+                    help="skip the one-thread oracle run of one field")
     ap.add_argument("--cpu-fields", type=int, default=0,
                     help="fields the oracle baseline transforms (0: as many as take about 15 s, "
                          "at most the workload's field count)")
@@ -50,13 +70,19 @@ def parse():
     return ap.parse_args()
 
 
+def say(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def kernel_bytes(plan, prec):
-    """Algorithmic HBM bytes per launch of each kernel (roofline)."""
+    """Algorithmic HBM bytes per launch of each kernel: the P̄ entries the method
+    needs, the spectral array and the Fourier array, each once (GEMMs); the
+    Fourier array and the grid, each once (FFTs)."""
     info = plan.info
     F = info.nfld
     cplx = 16 if prec == "fp64" else 8
     real = 8 if prec == "fp64" else 4
-    tab_el = {"fp64": 8, "fp32": 4, "bf16x3": 4}[prec]  # bf16 hi + lo
+    tab_el = {"fp64": 8, "fp32": 4, "bf16x3": 4, "fp16x3": 4}[prec]  # split forms: hi + lo halves
     nspec, npts, nfour = info.nspec, info.npts, info.nfour
     tables = tab_entries(plan) * tab_el
     four = F * nfour * cplx
@@ -79,32 +105,71 @@ def tab_entries(plan):
     return tot
 
 
-def run_form(torch, shtx, wl, prec, steps, warmup, spec_host, autotune):
-    plan = shtx.Plan(wl.trunc, wl.grid, wl.nlat, wl.nfld, prec, nlon_full=wl.nlon_full, timing=True,
-                     autotune=autotune)
-    spec = spec_host.to(plan.complex_dtype).cuda()
-    grid = torch.empty((wl.nfld, plan.npts), dtype=plan.real_dtype, device="cuda")
-    out = torch.empty_like(spec)
+def graph_steps(torch, stream, steps, warmup, fn):
+    """Run `fn` (one step of graph launches on `stream`) warmup + steps times;
+    HIP events around each timed step.  Returns per-step ms and the wall time."""
     for _ in range(warmup):
-        plan.inv(spec, out=grid)
-        plan.dir(grid, out=out)
-    torch.cuda.synchronize()
-    plan.timing_reset()
-    torch.cuda.synchronize()
+        fn()
+    stream.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.inv(spec, out=grid)
-        plan.dir(grid, out=out)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms, cnt = plan.timing_read()
-    kern = {k: (float(ms[i]) / max(int(cnt[i]), 1)) for i, k in enumerate(KERNELS)}
-    res = {
-        "plan": plan, "seconds": dt, "ms_per_step": 1e3 * dt / steps,
-        "fields_per_s": wl.nfld * steps / dt, "kernel_ms": kern,
-        "grid": grid, "spec_out": out,
-        "legendre_flops": float(plan.info.legendre_flops),
-    }
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    stream.synchronize()
+    wall = time.perf_counter() - t0
+    return [a.elapsed_time(b) for a, b in ev], wall
+
+
+def run_form(torch, shtx, wl, prec, steps, warmup, kernel_steps, spec_host, autotune, pair):
+    stream = torch.cuda.Stream()  # graph replay needs a non-default stream
+    with torch.cuda.stream(stream):
+        plan = shtx.Plan(wl.trunc, wl.grid, wl.nlat, wl.nfld, prec, nlon_full=wl.nlon_full, graph=True,
+                         timing=True, autotune=autotune)
+        spec = spec_host.to(plan.complex_dtype).to("cuda", non_blocking=False)
+        grid = torch.empty((wl.nfld, plan.npts), dtype=plan.real_dtype, device="cuda")
+        out = torch.empty_like(spec)
+        adj = torch.empty_like(spec)
+        stream.synchronize()
+
+        def step():
+            plan.inv(spec, out=grid)
+            plan.dir(grid, out=out)
+
+        # 1. product path: graph replay, events around each step
+        plan.timing_enable(False)
+        ms, wall = graph_steps(torch, stream, steps, warmup, step)
+        res = {
+            "plan": plan, "grid": grid, "spec_out": out, "legendre_flops": float(plan.info.legendre_flops),
+            "step_ms": ms, "ms_median": statistics.median(ms), "ms_min": min(ms), "wall_s": wall,
+            "fields_per_s": wl.nfld / (statistics.median(ms) * 1e-3),
+        }
+        if pair:
+            def pair_step():
+                plan.inv(spec, out=grid)
+                plan.inv_adj(grid, out=adj)
+            pms, pwall = graph_steps(torch, stream, steps, 1, pair_step)
+            res["pair"] = {"ms_median": statistics.median(pms), "ms_min": min(pms),
+                           "fields_per_s": wl.nfld / (statistics.median(pms) * 1e-3),
+                           "wall_fields_per_s": wl.nfld * steps / pwall}
+            res["adj_out"] = adj
+        # 2. kernel breakdown: eager launches with per-kernel events
+        plan.timing_enable(True)
+        step()
+        stream.synchronize()
+        plan.timing_reset()
+        for _ in range(kernel_steps):
+            step()
+        stream.synchronize()
+        kms, cnt = plan.timing_read()
+        res["kernel_ms"] = {k: (float(kms[i]) / max(int(cnt[i]), 1)) for i, k in enumerate(KERNELS)}
+        plan.timing_enable(False)
+        # the outputs the error check reads come from the graph path
+        step()
+        if pair:
+            plan.inv_adj(grid, out=adj)
+        stream.synchronize()
     return res
 
 
@@ -118,13 +183,14 @@ def roofline_for(res, prec):
     plan = res["plan"]
     nbytes = kernel_bytes(plan, prec)
     flops = res["legendre_flops"]
-    peak_tf = {"fp64": PEAK["fp64_TF"], "fp32": PEAK["fp32_TF"], "bf16x3": PEAK["bf16_TF"]}[prec]
+    peak_tf = PEAK_TF[prec]
     out = {}
     for k, t in res["kernel_ms"].items():
         if k.startswith("legendre"):
             ach = flops / (t * 1e-3) / 1e12
             out[k] = {"bound": "mfma", "achieved": ach, "peak": peak_tf, "unit": "TFLOP/s",
                       "frac": ach / peak_tf, "ms": t, "hbm_GBps": nbytes[k] / (t * 1e-3) / 1e9,
+                      "hbm_frac": nbytes[k] / (t * 1e-3) / 1e9 / PEAK["hbm_GBps"],
                       "algorithmic_bytes": nbytes[k], "algorithmic_flops": flops}
         else:
             ach = nbytes[k] / (t * 1e-3) / 1e9
@@ -142,51 +208,76 @@ def traffic_for(kernel, workload, prec):
     if not os.path.exists(path):
         return None
     try:
-        rec = json.load(open(path))
-        if rec.get("workload") != workload or rec.get("prec") != prec:
-            return None
+        recs = json.load(open(path))
+        if isinstance(recs, dict):
+            recs = [recs]
         from paper_1908_06097_amd.build import build_id
-        if rec.get("library_build_id") != build_id():
-            return None
-        k = rec["kernels"][kernel]
-        src = open(os.path.join(ROOT, "paper_1908_06097_amd", "csrc", k["source"]), "rb").read()
-        if hashlib.sha256(src).hexdigest() != k["source_sha256"]:
-            return None
-        return k["bytes_per_launch"]
+        for rec in recs:
+            if rec.get("workload") != workload or rec.get("prec") != prec:
+                continue
+            if rec.get("library_build_id") != build_id():
+                return None
+            k = rec["kernels"][kernel]
+            src = open(os.path.join(ROOT, "paper_1908_06097_amd", "csrc", k["source"]), "rb").read()
+            if hashlib.sha256(src).hexdigest() != k["source_sha256"]:
+                return None
+            return k["bytes_per_launch"]
     except Exception:
         return None
+    return None
 
 
-def cpu_baseline(wl, nfields, spec_np, target_s=15.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, nfields, spec_np, single_core, target_s=15.0):
     """The oracle (inverse then direct) on a bounded sample of the workload's
-    fields: `nfields` of them, or, if 0, one field and then as many more as
-    bring the sample to about `target_s` seconds."""
+    fields on every host thread: `nfields` of them, or, if 0, one field and
+    then as many more as bring the sample to about `target_s` seconds; then,
+    unless disabled, one field on one thread."""
     import numpy as np
     import oracle
     nlon = wl.ring_lengths()
+    cores = oracle.max_threads()
     t0 = time.perf_counter()
     n = max(nfields, 1)
-    g = oracle.inv(wl.trunc, nlon, spec_np[:n])
-    b = oracle.dir(wl.trunc, nlon, g)
+    g = oracle.inv(wl.trunc, nlon, spec_np[:n], nthreads=cores)
+    b = oracle.dir(wl.trunc, nlon, g, nthreads=cores)
     dt = time.perf_counter() - t0
     if nfields == 0:
         more = min(wl.nfld, max(1, int(round(target_s / max(dt, 1e-6))))) - 1
         if more > 0:
             t1 = time.perf_counter()
-            g2 = oracle.inv(wl.trunc, nlon, spec_np[1:1 + more])
-            b2 = oracle.dir(wl.trunc, nlon, g2)
+            g2 = oracle.inv(wl.trunc, nlon, spec_np[1:1 + more], nthreads=cores)
+            b2 = oracle.dir(wl.trunc, nlon, g2, nthreads=cores)
             dt += time.perf_counter() - t1
             g, b = np.concatenate([g, g2]), np.concatenate([b, b2])
             n += more
-    return {"value": n / dt, "unit": "fields/s", "cores": oracle.max_threads(), "kind": "oracle",
-            "sample": f"inv+dir of {n} of the {wl.nfld} fields of {wl.name} (per-field cost is identical)",
-            "seconds": dt}, g, b, n
+    out = {"value": n / dt, "unit": "fields/s", "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"inv+dir of {n} of the {wl.nfld} fields of {wl.name} on {cores} threads "
+                     f"(per-field cost is identical)",
+           "seconds": dt}
+    if single_core:
+        say("cpu baseline: one field on one thread")
+        t1 = time.perf_counter()
+        g1 = oracle.inv(wl.trunc, nlon, spec_np[:1], nthreads=1)
+        oracle.dir(wl.trunc, nlon, g1, nthreads=1)
+        s1 = time.perf_counter() - t1
+        out["single_core"] = {"value": 1.0 / s1, "unit": "fields/s", "seconds": s1,
+                              "sample": f"inv+dir of field 0 of {wl.name} on 1 thread"}
+    return out, g, b, n, cores
 
 
-def errors_vs_oracle(torch, res, g_ref, b_ref, wl, nfields):
+def errors_vs_oracle(res, g_ref, b_ref, wl, nfields):
     import numpy as np
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from metrics import grid_errors, spec_errors
+    from error_metrics import grid_errors, spec_errors
     import oracle
     _, w = oracle.gauss(wl.nlat)
     g = res["grid"][:nfields].double().cpu().numpy()
@@ -195,6 +286,24 @@ def errors_vs_oracle(torch, res, g_ref, b_ref, wl, nfields):
     sm, sr = spec_errors(b, b_ref, wl.trunc)
     return {"fields": nfields, "inv_grid_e_max": float(gm.max()), "inv_grid_e_rms": float(gr.max()),
             "dir_spec_e_max": float(sm.max()), "dir_spec_e_rms": float(sr.max())}
+
+
+def pair_errors(res, c_ref, wl, nfields):
+    """inv_adj(inv(a)) on the sampled fields against the oracle's."""
+    import numpy as np
+    from error_metrics import spec_errors
+    c = res["adj_out"][:nfields].cpu().numpy().astype(np.complex128)
+    sm, sr = spec_errors(c, c_ref, wl.trunc)
+    return {"fields": nfields, "inv_adj_spec_e_max": float(sm.max()), "inv_adj_spec_e_rms": float(sr.max())}
+
+
+def form_summary(res, prec, wl):
+    rf = roofline_for(res, prec)
+    return {"fields_per_s": res["fields_per_s"], "ms_median": res["ms_median"], "ms_min": res["ms_min"],
+            "wall_fields_per_s": wl.nfld * len(res["step_ms"]) / res["wall_s"],
+            "kernel_ms": res["kernel_ms"], "tiles": tiles_of(res["plan"]),
+            "legendre_frac": {k: rf[k]["frac"] for k in rf if k.startswith("legendre")},
+            "fft_hbm_frac": {k: rf[k]["frac"] for k in rf if k.startswith("ring")}}
 
 
 def main():
@@ -217,12 +326,15 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    print(f"[bench] {wl.name}: generating {wl.nfld} seeded fields", file=sys.stderr, flush=True)
+    say(f"{wl.name}: generating {wl.nfld} seeded fields")
     spec_np = si.spectral_fields(wl.trunc, wl.key, range(wl.nfld))
     spec_host = torch.from_numpy(spec_np)
+    pair = not args.no_pair
 
-    print(f"[bench] headline form {args.prec}", file=sys.stderr, flush=True)
-    res = run_form(torch, shtx, wl, args.prec, args.steps, args.warmup, spec_host, not args.no_autotune)
+    say(f"headline form {args.prec}")
+    res = run_form(torch, shtx, wl, args.prec, args.steps, args.warmup, args.kernel_steps, spec_host,
+                   not args.no_autotune, pair)
+    say(f"  {res['fields_per_s']:.1f} fields/s (median {res['ms_median']:.3f} ms, min {res['ms_min']:.3f} ms)")
     roof = roofline_for(res, args.prec)
     dom = max(roof, key=lambda k: roof[k]["ms"])
     d = roof[dom]
@@ -235,42 +347,50 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": res["ms_per_step"],
+        "ms_per_step": res["ms_median"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}[args.prec],
+        "dtype": DTYPE[args.prec],
         "data": "synthetic",
         "config": {"workload": wl.name, "trunc": wl.trunc, "grid": f"O{wl.nlat // 2}" if wl.grid == "octahedral"
                    else f"full {wl.nlat}x{wl.nlon_full}", "nlat": wl.nlat, "fields": wl.nfld,
                    "legendre_form": args.prec, "fft_dtype": "f64" if args.prec == "fp64" else "f32",
                    "tiles": tiles_of(res["plan"])},
+        "timing": {"path": "hipGraph replay, one inverse and one direct graph per step, non-default stream",
+                   "ms_median": res["ms_median"], "ms_min": res["ms_min"],
+                   "wall_fields_per_s": wl.nfld * args.steps / res["wall_s"],
+                   "kernel_breakdown": f"{args.kernel_steps} eager steps, library HIP events per kernel"},
         "legendre_tflops": res["legendre_flops"] * 2 / (
             (res["kernel_ms"]["legendre_inverse_gemm"] + res["kernel_ms"]["legendre_direct_gemm"]) * 1e-3) / 1e12,
         "roofline": roofline,
         "kernels": roof,
         "plan_seconds": float(res["plan"].info.plan_seconds),
     }
+    if pair:
+        line["pair_fwd_adj"] = dict(res["pair"], what="inv_trans then inv_trans_adj of its grids (graph replay)")
     if not args.no_cpu_baseline:
-        print(f"[bench] cpu baseline: oracle on {args.cpu_fields or 'about 15 s of'} field(s)", file=sys.stderr,
-              flush=True)
-        cb, g_ref, b_ref, n_ref = cpu_baseline(wl, args.cpu_fields, spec_np)
+        say(f"cpu baseline: oracle on {args.cpu_fields or 'about 15 s of'} field(s)")
+        cb, g_ref, b_ref, n_ref, cores = cpu_baseline(wl, args.cpu_fields, spec_np, not args.no_single_core)
         line["cpu_baseline"] = cb
-        line["error_vs_oracle"] = errors_vs_oracle(torch, res, g_ref, b_ref, wl, n_ref)
+        line["error_vs_oracle"] = errors_vs_oracle(res, g_ref, b_ref, wl, n_ref)
+        if pair:
+            import oracle
+            c_ref = oracle.inv_adj(wl.trunc, wl.ring_lengths(), g_ref, nthreads=cores)
+            line["pair_fwd_adj"]["error_vs_oracle"] = pair_errors(res, c_ref, wl, n_ref)
     res["plan"].close()
     del res
     torch.cuda.empty_cache()
 
     forms = {}
     for prec in [p for p in args.forms.split(",") if p and p != "none" and p != args.prec]:
-        print(f"[bench] form {prec}", file=sys.stderr, flush=True)
-        r = run_form(torch, shtx, wl, prec, args.form_steps, 1, spec_host, not args.no_autotune)
-        rf = roofline_for(r, prec)
-        forms[prec] = {"fields_per_s": r["fields_per_s"], "ms_per_step": r["ms_per_step"],
-                       "kernel_ms": r["kernel_ms"], "tiles": tiles_of(r["plan"]),
-                       "legendre_frac": {k: rf[k]["frac"] for k in rf if k.startswith("legendre")}}
+        say(f"form {prec}")
+        r = run_form(torch, shtx, wl, prec, args.form_steps, 1, max(2, args.kernel_steps // 2), spec_host,
+                     not args.no_autotune, False)
+        forms[prec] = form_summary(r, prec, wl)
+        say(f"  {r['fields_per_s']:.1f} fields/s")
         if not args.no_cpu_baseline:
-            forms[prec]["error_vs_oracle"] = errors_vs_oracle(torch, r, g_ref, b_ref, wl, n_ref)
+            forms[prec]["error_vs_oracle"] = errors_vs_oracle(r, g_ref, b_ref, wl, n_ref)
         r["plan"].close()
         del r
         torch.cuda.empty_cache()

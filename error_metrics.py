@@ -1,4 +1,5 @@
-"""Error metrics for comparing transform outputs with the FP64 oracle.
+"""Error metrics for comparing transform outputs with the FP64 oracle (used by
+the tests and the benchmark; no transform arithmetic).
 
 Spectral: e_max = max|a_hat - a| / max|a|, e_rms = sqrt(sum c_m |a_hat - a|^2 /
 sum c_m |a|^2) with c_0 = 1, c_m = 2 (the area-weighted grid RMS by Parseval).

@@ -43,9 +43,13 @@
  * Calls are asynchronous on the HIP stream passed (NULL = the default
  * stream); a plan may be used from one stream at a time because its
  * workspace is shared by every call.  Inputs are never modified; an output
- * that overlaps an input is rejected.  Functions return SHTX_OK or a negative
- * code; no C++ exception crosses this interface.  Device faults surface on
- * the next synchronisation.
+ * that overlaps an input, a pointer that is not 16-byte aligned, and a
+ * pointer that is not device (or managed) memory of the plan's device are
+ * rejected with SHTX_EINVAL before anything is launched.  Functions return
+ * SHTX_OK or a negative code; no C++ exception crosses this interface.
+ * Device faults surface on the next synchronisation.  Destroying a plan or
+ * changing its shapes waits for the plan's last transform call (not for the
+ * rest of the device).
  */
 #ifndef SHTX_H
 #define SHTX_H
@@ -118,17 +122,19 @@ int shtx_plan_check(int trunc, int grid, int nlat, int nlon_full, int nfld, int 
 /* Like shtx_plan_check, with explicit GEMM tile shapes (rows x columns of
  * the inverse- and direct-shaped launches; one of the shapes the autotuner
  * considers for the precision) and ring-FFT blocking `fft_cap` (LDS complex
- * values per block, 1 .. 6144).  A shape without a kernel instantiation is
+ * values per block, 1 .. 8192).  A shape without a kernel instantiation is
  * SHTX_EUNSUPPORTED; fft_cap out of range is SHTX_EINVAL. */
 int shtx_plan_check_shapes(int trunc, int grid, int nlat, int nlon_full, int nfld, int prec, int inv_bm,
                            int inv_bn, int dir_bm, int dir_bn, int fft_cap, shtx_info *out);
 
 /* Pin the GEMM tile shapes and ring-FFT blocking of an existing plan (for
  * example shapes chosen by an external tuner), with the same meaning and
- * checks as shtx_plan_check_shapes.  Synchronises the device first; no
- * transform of this plan may be in flight on another thread.  On error the
- * plan keeps working only if the return is SHTX_EINVAL or SHTX_EUNSUPPORTED
- * (nothing was changed). */
+ * checks as shtx_plan_check_shapes.  Waits for the plan's last transform
+ * first; no transform of this plan may be issued concurrently from another
+ * thread.  New work lists are checked and uploaded into new device buffers
+ * before the plan's are replaced, so on any error (SHTX_EINVAL,
+ * SHTX_EUNSUPPORTED, SHTX_ENOMEM, SHTX_EHIP) the plan is unchanged and keeps
+ * working. */
 int shtx_plan_set_shapes(shtx_plan p, int inv_bm, int inv_bn, int dir_bm, int dir_bn, int fft_cap);
 
 /* Host copies of plan geometry: nlon[nlat] ring lengths. */
@@ -154,7 +160,11 @@ int shtx_inv_trans_adj(shtx_plan p, const void *grid_d, void *spec_d, void *hip_
 int shtx_dir_trans_adj(shtx_plan p, const void *spec_d, void *grid_d, void *hip_stream);
 
 /* Kernel timing.  With SHTX_FLAG_TIMING at plan creation every transform
- * call records HIP events around each of its kernels on the call's stream.
+ * call records HIP events around each of its kernels on the call's stream
+ * (and runs eagerly, not as a graph) while timing is enabled, which it is
+ * from creation; shtx_timing_enable(p, 0) turns it off (graph replay, if
+ * the plan has SHTX_FLAG_GRAPH, resumes) and (p, 1) on again.  It returns
+ * SHTX_EINVAL for a plan made without SHTX_FLAG_TIMING.
  * shtx_timing_read synchronises on the recorded events and returns, per
  * kernel kind, the summed duration in milliseconds and the launch count:
  * index 0 inverse-shaped Legendre GEMM (inv_trans, dir_trans_adj),
@@ -163,6 +173,7 @@ int shtx_dir_trans_adj(shtx_plan p, const void *spec_d, void *grid_d, void *hip_
  * 4096 launches are recorded between resets; later ones are not timed. */
 #define SHTX_FLAG_TIMING 2u
 int shtx_timing_reset(shtx_plan p);
+int shtx_timing_enable(shtx_plan p, int on);
 int shtx_timing_read(shtx_plan p, double *ms_sum, int32_t *count);
 
 int shtx_plan_destroy(shtx_plan p);

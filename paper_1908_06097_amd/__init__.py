@@ -30,7 +30,7 @@ _lib = None
 
 _EXPORTS = ("shtx_plan_create", "shtx_plan_check", "shtx_plan_check_shapes", "shtx_plan_set_shapes", "shtx_plan_info", "shtx_plan_ring_lengths", "shtx_plan_nodes",
             "shtx_plan_legendre", "shtx_inv_trans", "shtx_dir_trans", "shtx_inv_trans_adj",
-            "shtx_dir_trans_adj", "shtx_timing_reset", "shtx_timing_read", "shtx_plan_destroy",
+            "shtx_dir_trans_adj", "shtx_timing_reset", "shtx_timing_enable", "shtx_timing_read", "shtx_plan_destroy",
             "shtx_strerror")
 
 
@@ -68,6 +68,7 @@ def load_library():
     for name in ("shtx_inv_trans", "shtx_dir_trans", "shtx_inv_trans_adj", "shtx_dir_trans_adj"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp]
     lib.shtx_timing_reset.argtypes = [vp]
+    lib.shtx_timing_enable.argtypes = [vp, i32]
     lib.shtx_timing_read.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
     lib.shtx_plan_destroy.argtypes = [vp]
     lib.shtx_strerror.argtypes = [i32]
@@ -181,8 +182,11 @@ class Plan:
             shape, dt = (self.nfld, self.npts), self.real_dtype
         if out is None:
             return torch.empty(shape, dtype=dt, device=device)
+        if not out.is_cuda or out.device != device:
+            raise ShtxError(f"output must be a device tensor on {device}, got {out.device}")
         if out.dtype != dt or tuple(out.shape) != shape or not out.is_contiguous():
-            raise ShtxError("bad output tensor")
+            raise ShtxError(f"output must be a contiguous {dt} {list(shape)} tensor, got {out.dtype} "
+                            f"{list(out.shape)}")
         return out
 
     def _run(self, fn, x, kind_in, kind_out, out):
@@ -213,6 +217,10 @@ class Plan:
     # -- timing -------------------------------------------------------------------
     def timing_reset(self):
         _check(load_library().shtx_timing_reset(self._h), "timing_reset")
+
+    def timing_enable(self, on=True):
+        """Per-kernel event timing on or off (plans made with timing=True)."""
+        _check(load_library().shtx_timing_enable(self._h, 1 if on else 0), "timing_enable")
 
     def timing_read(self):
         """Summed kernel milliseconds and launch counts: [inv GEMM, dir GEMM, c2r, r2c]."""

@@ -72,17 +72,6 @@ void cache_store(const char *path, const std::string &key, const TuneResult &r)
     std::fclose(f);
 }
 
-template <class T>
-hipError_t reupload(T **dst, const std::vector<T> &src)
-{
-    if (*dst) (void)hipFree(*dst);
-    *dst = nullptr;
-    if (src.empty()) return hipSuccess;
-    hipError_t e = hipMalloc(dst, sizeof(T) * src.size());
-    if (e != hipSuccess) return e;
-    return hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
-}
-
 // Mean milliseconds of `reps` runs of `fn` after one untimed run.
 template <class Fn>
 double time_ms(hipStream_t s, hipEvent_t a, hipEvent_t b, int reps, Fn fn)
@@ -115,7 +104,7 @@ int autotune_plan(Plan &p, hipStream_t s)
         void *spec = nullptr, *grid = nullptr;
         hipEvent_t ea = nullptr, eb = nullptr;
         int rc = SHTX_OK;
-        const int reps = 2;
+        const int reps = 3;
         auto fail = [&](int code) {
             rc = code;
             return code;
@@ -124,9 +113,11 @@ int autotune_plan(Plan &p, hipStream_t s)
             hipMalloc(&grid, rbytes * p.nfld * p.npts) != hipSuccess || hipEventCreate(&ea) != hipSuccess ||
             hipEventCreate(&eb) != hipSuccess)
             fail(SHTX_ENOMEM);
-        if (rc == SHTX_OK && (hipMemsetAsync(spec, 0, cbytes * p.nfld * p.nspec, s) != hipSuccess ||
-                              hipMemsetAsync(grid, 0, rbytes * p.nfld * p.npts, s) != hipSuccess ||
-                              hipMemsetAsync(p.d_four, 0, cbytes * p.nfld * p.nfour, s) != hipSuccess))
+        // nonzero finite operands (every byte 0x3C: 0.0115 in single, 1.5e-18
+        // in double precision), so that the timed kernels do real arithmetic
+        if (rc == SHTX_OK && (hipMemsetAsync(spec, 0x3C, cbytes * p.nfld * p.nspec, s) != hipSuccess ||
+                              hipMemsetAsync(grid, 0x3C, rbytes * p.nfld * p.npts, s) != hipSuccess ||
+                              hipMemsetAsync(p.d_four, 0x3C, cbytes * p.nfld * p.nfour, s) != hipSuccess))
             fail(SHTX_EHIP);
 
         int cbm[8], cbn[8];
@@ -134,12 +125,10 @@ int autotune_plan(Plan &p, hipStream_t s)
         double bi = 1e300, bd = 1e300;
         // inverse-shaped and direct-shaped launches are tuned independently
         for (int c = 0; c < nc && rc == SHTX_OK; ++c) {
-            p.inv_bm = p.dir_bm = cbm[c];
-            p.inv_bn = p.dir_bn = cbn[c];
-            if (gemm_work_lists(p) != SHTX_OK) continue;
-            if (reupload(&p.d_inv_items, p.inv_items) != hipSuccess ||
-                reupload(&p.d_dir_items, p.dir_items) != hipSuccess) {
-                fail(SHTX_EHIP);
+            int arc = apply_shapes(p, cbm[c], cbn[c], cbm[c], cbn[c], p.fft_cap);
+            if (arc == SHTX_EINVAL || arc == SHTX_EUNSUPPORTED) continue;
+            if (arc != SHTX_OK) {
+                fail(arc);
                 break;
             }
             double ti = time_ms(s, ea, eb, reps, [&] { return launch_gemm_inverse(p, spec, p.d_four, s); });
@@ -164,9 +153,10 @@ int autotune_plan(Plan &p, hipStream_t s)
         double bf = 1e300;
         for (int cap : caps) {
             if (rc != SHTX_OK) break;
-            if (fft_blocking(p, cap) != SHTX_OK) continue;
-            if (reupload(&p.d_fft_items, p.fft_items) != hipSuccess) {
-                fail(SHTX_EHIP);
+            int arc = apply_shapes(p, p.inv_bm, p.inv_bn, p.dir_bm, p.dir_bn, cap);
+            if (arc == SHTX_EINVAL || arc == SHTX_EUNSUPPORTED) continue;
+            if (arc != SHTX_OK) {
+                fail(arc);
                 break;
             }
             double tf = time_ms(s, ea, eb, reps, [&] {
@@ -180,6 +170,7 @@ int autotune_plan(Plan &p, hipStream_t s)
                 best.fft_ms = tf;
             }
         }
+        if (hipStreamSynchronize(s) != hipSuccess) fail(SHTX_EHIP);
         if (spec) (void)hipFree(spec);
         if (grid) (void)hipFree(grid);
         if (ea) (void)hipEventDestroy(ea);
@@ -198,24 +189,107 @@ int autotune_plan(Plan &p, hipStream_t s)
     return rc;
 }
 
+namespace {
+
+// The plan state that apply_shapes rebuilds, kept so that a failed call can
+// put it back.
+struct ShapeState {
+    int inv_bm, inv_bn, dir_bm, dir_bn, inv_nmain, dir_nmain, inv_tail_bn, dir_tail_bn;
+    int fft_lds_bytes, fft_lds_max, fft_cap;
+    bool shapes_ok;
+    std::vector<GemmItem> inv_items, dir_items;
+    std::vector<FftItem> fft_items;
+    std::vector<int> fb;
+};
+
+ShapeState save_shapes(const Plan &p)
+{
+    ShapeState s{p.inv_bm,      p.inv_bn,      p.dir_bm,      p.dir_bn,   p.inv_nmain, p.dir_nmain,
+                 p.inv_tail_bn, p.dir_tail_bn, p.fft_lds_bytes, p.fft_lds_max, p.fft_cap, p.shapes_ok,
+                 p.inv_items,   p.dir_items,   p.fft_items,   {}};
+    for (const RingDesc &d : p.rings) s.fb.push_back(d.fb);
+    return s;
+}
+
+void restore_shapes(Plan &p, ShapeState &s)
+{
+    p.inv_bm = s.inv_bm;
+    p.inv_bn = s.inv_bn;
+    p.dir_bm = s.dir_bm;
+    p.dir_bn = s.dir_bn;
+    p.inv_nmain = s.inv_nmain;
+    p.dir_nmain = s.dir_nmain;
+    p.inv_tail_bn = s.inv_tail_bn;
+    p.dir_tail_bn = s.dir_tail_bn;
+    p.fft_lds_bytes = s.fft_lds_bytes;
+    p.fft_lds_max = s.fft_lds_max;
+    p.fft_cap = s.fft_cap;
+    p.shapes_ok = s.shapes_ok;
+    p.inv_items.swap(s.inv_items);
+    p.dir_items.swap(s.dir_items);
+    p.fft_items.swap(s.fft_items);
+    for (size_t j = 0; j < p.rings.size() && j < s.fb.size(); ++j) p.rings[j].fb = s.fb[j];
+}
+
+template <class T>
+hipError_t upload_new(T **dst, const std::vector<T> &src)
+{
+    *dst = nullptr;
+    if (src.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(dst, sizeof(T) * src.size());
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        return e;
+    }
+    e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(*dst);
+        *dst = nullptr;
+    }
+    return e;
+}
+
+}  // namespace
+
 int apply_shapes(Plan &p, int inv_bm, int inv_bn, int dir_bm, int dir_bn, int fft_cap)
 {
     const int maxcap = p.prec == SHTX_FP64 ? kFftCapF64 : kFftCapF32;
     if (fft_cap < 1 || fft_cap > maxcap) return SHTX_EINVAL;
     if (!gemm_tile_supported(p.prec, inv_bm, inv_bn) || !gemm_tile_supported(p.prec, dir_bm, dir_bn))
         return SHTX_EUNSUPPORTED;
+    ShapeState old = save_shapes(p);
     p.inv_bm = inv_bm;
     p.inv_bn = inv_bn;
     p.dir_bm = dir_bm;
     p.dir_bn = dir_bn;
     int rc = gemm_work_lists(p);
-    if (rc != SHTX_OK) return rc;
-    rc = fft_blocking(p, fft_cap);
-    if (rc != SHTX_OK) return rc;
-    if (!gemm_shapes_ok(p) || !fft_shapes_ok(p)) return SHTX_EUNSUPPORTED;
-    if (reupload(&p.d_inv_items, p.inv_items) != hipSuccess || reupload(&p.d_dir_items, p.dir_items) != hipSuccess ||
-        reupload(&p.d_fft_items, p.fft_items) != hipSuccess)
-        return SHTX_EHIP;
+    if (rc == SHTX_OK) rc = fft_blocking(p, fft_cap);
+    if (rc == SHTX_OK && (!gemm_shapes_ok(p) || !fft_shapes_ok(p))) rc = SHTX_EUNSUPPORTED;
+    if (rc != SHTX_OK) {
+        restore_shapes(p, old);
+        return rc;
+    }
+    // new device lists first; the plan's are replaced only if all succeed
+    GemmItem *di = nullptr, *dd = nullptr;
+    FftItem *df = nullptr;
+    hipError_t e = upload_new(&di, p.inv_items);
+    if (e == hipSuccess) e = upload_new(&dd, p.dir_items);
+    if (e == hipSuccess) e = upload_new(&df, p.fft_items);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        if (di) (void)hipFree(di);
+        if (dd) (void)hipFree(dd);
+        if (df) (void)hipFree(df);
+        restore_shapes(p, old);
+        return e == hipErrorOutOfMemory ? SHTX_ENOMEM : SHTX_EHIP;
+    }
+    if (p.d_inv_items) (void)hipFree(p.d_inv_items);
+    if (p.d_dir_items) (void)hipFree(p.d_dir_items);
+    if (p.d_fft_items) (void)hipFree(p.d_fft_items);
+    p.d_inv_items = di;
+    p.d_dir_items = dd;
+    p.d_fft_items = df;
+    p.shapes_ok = true;
     p.tuned = 0;
     return SHTX_OK;
 }

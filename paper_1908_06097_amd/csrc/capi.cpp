@@ -41,6 +41,35 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb)
 
 bool aligned16(const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; }
 
+// A transform's input and output must be device (or managed) memory on the
+// plan's device: a host pointer handed to the kernels would fault the GPU
+// instead of returning an error.
+bool device_memory(const void *q, int device)
+{
+    hipPointerAttribute_t at{};
+    if (hipPointerGetAttributes(&at, q) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    if (at.type == hipMemoryTypeManaged || at.isManaged) return true;
+    return at.type == hipMemoryTypeDevice && at.device == device;
+}
+
+// Remember the end of a transform's work on its stream, so that destroying
+// the plan or changing its shapes waits for exactly that work.  A stream the
+// caller is capturing records nothing here (the caller owns that graph).
+hipError_t mark_done(Plan &p, hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess) return e;
+    if (cs != hipStreamCaptureStatusNone) return hipSuccess;
+    return hipEventRecord(p.done, s);
+}
+
+// Wait for the last recorded transform of the plan.
+hipError_t wait_done(Plan &p) { return p.done ? hipEventSynchronize(p.done) : hipSuccess; }
+
 // Launch the kernels of one transform kind on stream s.
 hipError_t launch_kind(Plan &p, int kind, const void *in, void *out, hipStream_t s, bool timed)
 {
@@ -81,19 +110,33 @@ hipError_t launch_kind(Plan &p, int kind, const void *in, void *out, hipStream_t
     return e;
 }
 
-int run(shtx_plan h, int kind, const void *in, void *out, void *stream)
+// Argument checks shared by every transform entry point.
+int check_args(const Plan &p, int kind, const void *in, const void *out)
 {
-    if (!h || !in || !out) return SHTX_EINVAL;
-    Plan &p = h->p;
+    if (!in || !out || !p.shapes_ok) return SHTX_EINVAL;
     bool spec_in = kind == shtx::kInverse || kind == shtx::kDirectAdj;
     size_t nin = spec_in ? spec_bytes(p) : grid_bytes(p);
     size_t nout = spec_in ? grid_bytes(p) : spec_bytes(p);
     if (overlap(in, nin, out, nout)) return SHTX_EINVAL;
     if (!aligned16(in) || !aligned16(out)) return SHTX_EINVAL;
+    if (!device_memory(in, p.device) || !device_memory(out, p.device)) return SHTX_EINVAL;
+    return SHTX_OK;
+}
+
+int run(shtx_plan h, int kind, const void *in, void *out, void *stream)
+{
+    if (!h) return SHTX_EINVAL;
+    Plan &p = h->p;
+    int rc = check_args(p, kind, in, out);
+    if (rc != SHTX_OK) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    bool timed = (p.flags & SHTX_FLAG_TIMING) != 0;
+    bool timed = p.timing_on;
     bool graph = (p.flags & SHTX_FLAG_GRAPH) != 0 && !timed && s != nullptr;
-    if (!graph) return hip_status(launch_kind(p, kind, in, out, s, timed));
+    if (!graph) {
+        hipError_t e = launch_kind(p, kind, in, out, s, timed);
+        if (e == hipSuccess) e = mark_done(p, s);
+        return hip_status(e);
+    }
 
     Plan::GraphEntry &g = p.graphs[kind];
     if (!(g.exec && g.in == in && g.out == out && g.stream == s)) {
@@ -120,7 +163,9 @@ int run(shtx_plan h, int kind, const void *in, void *out, void *stream)
         g.out = out;
         g.stream = s;
     }
-    return hip_status(hipGraphLaunch(g.exec, s));
+    hipError_t e = hipGraphLaunch(g.exec, s);
+    if (e == hipSuccess) e = mark_done(p, s);
+    return hip_status(e);
 }
 
 }  // namespace
@@ -290,6 +335,13 @@ int shtx_timing_reset(shtx_plan h)
     return SHTX_OK;
 }
 
+int shtx_timing_enable(shtx_plan h, int on)
+{
+    if (!h || !(h->p.flags & SHTX_FLAG_TIMING)) return SHTX_EINVAL;
+    h->p.timing_on = on != 0;
+    return SHTX_OK;
+}
+
 int shtx_timing_read(shtx_plan h, double *ms_sum, int32_t *count)
 {
     if (!h) return SHTX_EINVAL;
@@ -317,7 +369,7 @@ int shtx_plan_set_shapes(shtx_plan h, int inv_bm, int inv_bn, int dir_bm, int di
     if (!h) return SHTX_EINVAL;
     Plan &p = h->p;
     // earlier transforms may still read the old work lists
-    hipError_t e = hipDeviceSynchronize();
+    hipError_t e = wait_done(p);
     if (e != hipSuccess) return hip_status(e);
     for (auto &g : p.graphs)
         if (g.exec) {
@@ -330,7 +382,7 @@ int shtx_plan_set_shapes(shtx_plan h, int inv_bm, int inv_bn, int dir_bm, int di
 int shtx_plan_destroy(shtx_plan h)
 {
     if (!h) return SHTX_EINVAL;
-    (void)hipDeviceSynchronize();
+    (void)wait_done(h->p);
     shtx::free_plan(h->p);
     delete h;
     return SHTX_OK;

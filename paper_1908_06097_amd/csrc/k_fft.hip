@@ -6,11 +6,12 @@
 // split/merge step around it.  The length-h DFT is a Stockham autosort
 // mixed-radix FFT (radices 16, 9, 8, 4, 2, 3 and the primes 5 to 23; 17 in
 // FP64) held in LDS, run in place: each pass reads its butterflies into
-// registers, synchronises, then writes.  One larger prime factor up to 191
-// runs as a general prime pass (below); other lengths go through Bluestein's
-// chirp
-// convolution at a length L = 2^a 3^b >= 2h - 1, with the filter spectrum
-// precomputed per ring length at plan time.  Only the kept wavenumbers
+// registers, synchronises, then writes.  One larger prime factor (up to 1021:
+// always up to 191, above that where the plan's cost model prefers it to
+// Bluestein) runs as a general prime pass on the matrix cores (below); other
+// lengths go through Bluestein's chirp convolution at a length L = 2^a 3^b
+// >= 2h - 1, with the filter spectrum precomputed per ring length at plan
+// time.  Only the kept wavenumbers
 // m <= M_j are read or written; they live in the Fourier workspace laid out
 // [ring][m][field], so a block's loads and stores are runs over fields.
 //
@@ -1026,31 +1027,38 @@ bool check_fft(const Plan &p, int cap)
 template <typename T, int CAP, bool C2R>
 hipError_t launch_fft(const Plan &p, const void *in, void *out, bool adjoint, hipStream_t s)
 {
-    if (!check_fft<T>(p, CAP)) {
-        if (std::getenv("SHTX_DEBUG")) std::fprintf(stderr, "shtx: ring-FFT launch shape check failed\n");
-        return hipErrorInvalidValue;
-    }
+    // the rings, passes and work list were checked against the kernels'
+    // limits (check_fft) when the plan's blocking was built
+    if (!p.shapes_ok || p.fft_items.empty()) return hipErrorInvalidValue;
     FftArgs a{p.d_rings, p.d_fft_items, p.d_passes, p.d_twid, in, out, p.nfld, adjoint ? 1 : 0, p.npts};
     auto kern = C2R ? k_fft_c2r<T, CAP> : k_fft_r2c<T, CAP>;
-    // raise the kernel's dynamic-LDS limit when a plan needs more than any
-    // earlier one (above 64 KiB it must be requested explicitly)
-    static int attr_bytes = 0;
-    int &ab = attr_bytes;
-    if (p.fft_lds_bytes > ab) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, p.fft_lds_bytes);
-        if (e != hipSuccess) {
-            if (std::getenv("SHTX_DEBUG"))
-                std::fprintf(stderr, "shtx: dynamic LDS limit %d bytes refused\n", p.fft_lds_bytes);
-            return e;
-        }
-        ab = p.fft_lds_bytes;
-    }
     kern<<<(int)p.fft_items.size(), kFftThreads, p.fft_lds_bytes, s>>>(a);
     return hipGetLastError();
 }
 
+// Dynamic LDS above 64 KiB must be allowed per kernel; allowing the whole
+// workgroup LDS once (a limit, not a reservation: occupancy follows the
+// LDS each launch asks for) keeps every plan's launches valid without
+// per-launch attribute calls.
+template <typename T, int CAP>
+hipError_t fft_allow_lds()
+{
+    constexpr int kMaxLds = 160 * 1024;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_fft_c2r<T, CAP>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_fft_r2c<T, CAP>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds);
+    return e;
+}
+
 }  // namespace
+
+hipError_t fft_prepare(const Plan &p)
+{
+    if (p.fft_lds_bytes > 160 * 1024) return hipErrorInvalidValue;
+    return p.prec == SHTX_FP64 ? fft_allow_lds<double, kFftCapF64>() : fft_allow_lds<float, kFftCapF32>();
+}
 
 bool fft_shapes_ok(const Plan &p)
 {

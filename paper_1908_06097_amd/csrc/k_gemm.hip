@@ -748,25 +748,16 @@ GemmArgs make_args(const Plan &p, bool inverse_shape, const void *in, void *out,
     return a;
 }
 
-// Host check that every tile of a work list reads and writes inside the
-// table, Fourier and spectral arrays for the given tile sizes.
-bool check_items_impl(const Plan &p, const std::vector<GemmItem> &items, bool inverse_shape, int bm, int bn,
-                      int bk);
-
-bool check_items(const Plan &p, const std::vector<GemmItem> &items, bool inverse_shape, int bm, int bn, int bk)
+// Host check that every tile of items [first, first + count) of a work list
+// reads and writes inside the table, Fourier and spectral arrays for the
+// given tile sizes.  Run when a plan's work lists are built, not per launch.
+bool check_items(const Plan &p, const std::vector<GemmItem> &items, size_t first, size_t count, bool inverse_shape,
+                 int bm, int bn, int bk)
 {
-    bool ok = check_items_impl(p, items, inverse_shape, bm, bn, bk);
-    if (!ok && std::getenv("SHTX_DEBUG"))
-        std::fprintf(stderr, "shtx: Legendre GEMM work-list check failed (%s)\n", inverse_shape ? "inverse" : "direct");
-    return ok;
-}
-
-bool check_items_impl(const Plan &p, const std::vector<GemmItem> &items, bool inverse_shape, int bm, int bn,
-                      int bk)
-{
-    if (items.empty() || items.size() % kXcds) return false;
+    if (count == 0 || count % kXcds || first + count > items.size()) return false;
     int ncol = 2 * p.nfld;
-    for (const GemmItem &it : items) {
+    for (size_t q = first; q < first + count; ++q) {
+        const GemmItem &it = items[q];
         if (it.m < 0) continue;
         if (it.m > p.trunc) return false;
         const MBlock &b = p.mb[it.m];
@@ -788,13 +779,13 @@ bool check_items_impl(const Plan &p, const std::vector<GemmItem> &items, bool in
 bool check_work_list(const Plan &p, const std::vector<GemmItem> &items, int nmain, bool inverse_shape, int bm,
                      int bn, int tail_bn, int bk)
 {
-    if (nmain < 1 || nmain > (int)items.size()) return false;
-    const std::vector<GemmItem> main(items.begin(), items.begin() + nmain);
-    if (!check_items(p, main, inverse_shape, bm, bn, bk)) return false;
-    if (nmain == (int)items.size()) return true;
-    if (tail_bn <= 0) return false;
-    const std::vector<GemmItem> tail(items.begin() + nmain, items.end());
-    return check_items(p, tail, inverse_shape, bm, tail_bn, bk);
+    bool ok = nmain >= 1 && nmain <= (int)items.size() &&
+              check_items(p, items, 0, (size_t)nmain, inverse_shape, bm, bn, bk);
+    if (ok && nmain < (int)items.size())
+        ok = tail_bn > 0 && check_items(p, items, (size_t)nmain, items.size() - nmain, inverse_shape, bm, tail_bn, bk);
+    if (!ok && std::getenv("SHTX_DEBUG"))
+        std::fprintf(stderr, "shtx: Legendre GEMM work-list check failed (%s)\n", inverse_shape ? "inverse" : "direct");
+    return ok;
 }
 
 
@@ -826,9 +817,10 @@ hipError_t launch_mfma_part(const GemmArgs &args, int first, int count, int bm, 
 template <typename T, int BK, bool INV>
 hipError_t launch_mfma(const Plan &p, const GemmArgs &a, int bm, int bn, hipStream_t s)
 {
+    // the work lists were checked against these shapes when they were built
     const std::vector<GemmItem> &items = INV ? p.inv_items : p.dir_items;
     const int nmain = INV ? p.inv_nmain : p.dir_nmain, tail_bn = INV ? p.inv_tail_bn : p.dir_tail_bn;
-    if (!check_work_list(p, items, nmain, INV, bm, bn, tail_bn, BK)) return hipErrorInvalidValue;
+    if (!p.shapes_ok || nmain < 1) return hipErrorInvalidValue;
     hipError_t e = launch_mfma_part<T, BK, INV>(a, 0, nmain, bm, bn, s);
     if (e != hipSuccess || nmain == (int)items.size()) return e;
     return launch_mfma_part<T, BK, INV>(a, nmain, (int)items.size() - nmain, bm, tail_bn, s);
@@ -839,7 +831,7 @@ hipError_t launch_bf16(const Plan &p, const GemmArgs &a, int bm, int bn, hipStre
 {
     const std::vector<GemmItem> &items = INV ? p.inv_items : p.dir_items;
     const int grid = (int)items.size();
-    if (!check_items(p, items, INV, bm, bn, 32)) return hipErrorInvalidValue;
+    if (!p.shapes_ok || grid < 1) return hipErrorInvalidValue;
     if (bm == 128 && bn == 128)
         k_leg_bf16x3<128, 128, 32, INV><<<grid, 256, 0, s>>>(a);
     else if (bm == 64 && bn == 128)

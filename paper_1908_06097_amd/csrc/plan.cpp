@@ -166,6 +166,7 @@ void free_plan(Plan &p)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     for (auto e : p.ev_start) (void)hipEventDestroy(e);
     for (auto e : p.ev_stop) (void)hipEventDestroy(e);
+    if (p.done) (void)hipEventDestroy(p.done);
     p = Plan();
 }
 
@@ -513,6 +514,7 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
     if (rc != SHTX_OK) return rc;
     if (!gemm_shapes_ok(p) || !fft_shapes_ok(p)) return SHTX_EUNSUPPORTED;
     const int N = trunc, NL = nlat / 2;
+    PLAN_TRY(hipGetDevice(&p.device));
 
     // ---- Gauss nodes and Legendre tables (device, FP64) ---------------------
     PLAN_TRY(hipMalloc(&p.d_mu, sizeof(double) * nlat));
@@ -578,10 +580,12 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
             PLAN_TRY(upload(reinterpret_cast<float **>(&p.d_ring_q), q));
         }
     }
-    PLAN_TRY(upload(&p.d_fft_items, p.fft_items));
     PLAN_TRY(upload(&p.d_passes, p.passes));
-    PLAN_TRY(upload(&p.d_inv_items, p.inv_items));
-    PLAN_TRY(upload(&p.d_dir_items, p.dir_items));
+    // checks every launch shape once more and uploads the work lists
+    rc = apply_shapes(p, p.inv_bm, p.inv_bn, p.dir_bm, p.dir_bn, p.fft_cap);
+    if (rc != SHTX_OK) return rc;
+    PLAN_TRY(fft_prepare(p));
+    PLAN_TRY(hipEventCreateWithFlags(&p.done, hipEventDisableTiming));
 
     PLAN_TRY(hipMalloc(&p.d_four, (size_t)p.nfour * nfld * celem));
 
@@ -591,6 +595,7 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
     }
 
     if (flags & SHTX_FLAG_TIMING) {
+        p.timing_on = true;
         p.ev_start.resize(Plan::kMaxTimed);
         p.ev_stop.resize(Plan::kMaxTimed);
         p.ev_kind.resize(Plan::kMaxTimed);

@@ -131,6 +131,13 @@ struct Plan {
     int fft_lds_max = 0;  // complex entries of LDS the largest FFT block may use
     int fft_cap = 0;      // LDS complex values per FFT block the blocking was made for
     int tuned = 0;        // 0 default tiles, 1 timed by the autotuner, 2 from the tune cache
+    // True once every kernel's work list and launch shape has passed the host
+    // checks and the device copies of the lists match them; launches check
+    // only this flag, so the per-item checks run at plan time, not per call.
+    bool shapes_ok = false;
+    int device = -1;              // HIP device the plan's memory lives on
+    hipEvent_t done = nullptr;    // recorded after each transform's launches
+    bool timing_on = false;       // record kernel events (plans made with SHTX_FLAG_TIMING)
 
     // Device memory.
     double *d_mu = nullptr, *d_w = nullptr;  // nlat
@@ -205,9 +212,14 @@ int gemm_work_lists(Plan &p);
 // Time the candidate GEMM tile shapes and FFT blockings on this plan and keep
 // the fastest (or take them from the tune cache); uploads the work lists.
 int autotune_plan(Plan &p, hipStream_t s);
-// Set the GEMM tile shapes and FFT blocking of a built plan (rebuilds and
-// uploads the work lists; the caller makes sure no transform is in flight).
+// Set the GEMM tile shapes and FFT blocking of a built plan: rebuilds the
+// work lists, checks every launch shape, uploads the lists into new device
+// buffers and only then replaces the plan's (the caller makes sure no
+// transform is in flight).  On any error the plan is left as it was.
 int apply_shapes(Plan &p, int inv_bm, int inv_bn, int dir_bm, int dir_bn, int fft_cap);
+// Let the ring-FFT kernels of the plan's precision use the whole LDS of a
+// workgroup as dynamic LDS (set per device at plan creation).
+hipError_t fft_prepare(const Plan &p);
 
 // Host-side Bluestein filter: out[k] = DFT_L(b)[k] / L in long double, b the
 // conjugate chirp wrapped to length L.

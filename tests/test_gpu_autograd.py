@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import synth_inputs as si
-from metrics import spec_errors
+from error_metrics import spec_errors
 
 pytestmark = pytest.mark.gpu
 

@@ -48,6 +48,34 @@ def test_graph_replay_matches_eager(prec):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_graph_path_matches_oracle(prec):
+    """The hipGraph replay path (the one the benchmark times) against the
+    oracle on a multi-tile shape, every transform kind, four replays each."""
+    from test_gpu_transforms import _check_all
+    torch, shtx = _env()
+    N, nlat, F = 159, 320, 70
+    plan = shtx.Plan(N, "octahedral", nlat, F, prec, graph=True)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        print(f"graph path T{N} O{nlat // 2} F={F} {prec}", flush=True)
+        _check_all(plan, N, plan.ring_lengths(), 11, range(F), prec)
+        # replays of the cached graphs, with eager work between them, stay equal
+        a = _spec(torch, plan, key=11)
+        g0 = plan.inv(a).clone()
+        s0 = plan.dir(g0).clone()
+        g, s = torch.empty_like(g0), torch.empty_like(s0)
+        for rep in range(4):
+            plan.inv(a, out=g)
+            plan.dir(g, out=s)
+            side.synchronize()
+            assert torch.equal(g, g0) and torch.equal(s, s0), rep
+            g.add_(1.0)
+            s.zero_()
+    torch.cuda.synchronize()
+    plan.close()
+
+
 def test_bitwise_deterministic():
     torch, shtx = _env()
     plan = shtx.Plan(159, "octahedral", 320, 33, "fp32")
@@ -130,7 +158,14 @@ def test_argument_errors():
         plan.inv(a[:1])
     with pytest.raises(shtx.ShtxError):
         plan.inv(a.cpu())
+    with pytest.raises(shtx.ShtxError):  # host output tensor: refused before any launch
+        plan.inv(a, out=torch.empty((plan.nfld, plan.npts), dtype=torch.float32))
     lib = shtx.load_library()
+    # a host pointer through the C ABI is refused by the library itself
+    host = np.zeros(plan.npts * plan.nfld + 16, dtype=np.float32)
+    hp = ctypes.c_void_p((host.ctypes.data + 15) // 16 * 16)
+    assert lib.shtx_inv_trans(plan._h, ctypes.c_void_p(a.data_ptr()), hp, None) == -1
+    assert lib.shtx_dir_trans(plan._h, hp, ctypes.c_void_p(a.data_ptr()), None) == -1
     buf = torch.zeros(max(plan.npts, 2 * plan.nspec) * 2, dtype=torch.float32, device="cuda")
     p = ctypes.c_void_p(buf.data_ptr())
     rc = lib.shtx_inv_trans(plan._h, p, p, None)  # output overlaps input
