@@ -14,21 +14,11 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
 void free_plan(Plan &p);
 }  // namespace shtx
 
-struct shtx_plan_s {
-    shtx::Plan p;
-};
-
 using shtx::Plan;
 
-namespace {
+namespace shtx {
 
-int hip_status(hipError_t e)
-{
-    if (e == hipSuccess) return SHTX_OK;
-    (void)hipGetLastError();
-    if (std::getenv("SHTX_DEBUG")) std::fprintf(stderr, "shtx: HIP error %d: %s\n", (int)e, hipGetErrorString(e));
-    return SHTX_EHIP;
-}
+namespace {
 
 size_t spec_bytes(const Plan &p) { return (size_t)p.nfld * p.nspec * (p.prec == SHTX_FP64 ? 16 : 8); }
 size_t grid_bytes(const Plan &p) { return (size_t)p.nfld * p.npts * (p.prec == SHTX_FP64 ? 8 : 4); }
@@ -55,6 +45,8 @@ bool device_memory(const void *q, int device)
     return at.type == hipMemoryTypeDevice && at.device == device;
 }
 
+}  // namespace
+
 // Remember the end of a transform's work on its stream, so that destroying
 // the plan or changing its shapes waits for exactly that work.  A stream the
 // caller is capturing records nothing here (the caller owns that graph).
@@ -69,6 +61,35 @@ hipError_t mark_done(Plan &p, hipStream_t s)
 
 // Wait for the last recorded transform of the plan.
 hipError_t wait_done(Plan &p) { return p.done ? hipEventSynchronize(p.done) : hipSuccess; }
+
+// Argument checks shared by every transform entry point.
+int check_args(const Plan &p, int kind, const void *in, const void *out)
+{
+    if (!in || !out || !p.shapes_ok) return SHTX_EINVAL;
+    bool spec_in = kind == kInverse || kind == kDirectAdj;
+    size_t nin = spec_in ? spec_bytes(p) : grid_bytes(p);
+    size_t nout = spec_in ? grid_bytes(p) : spec_bytes(p);
+    if (overlap(in, nin, out, nout)) return SHTX_EINVAL;
+    if (!aligned16(in) || !aligned16(out)) return SHTX_EINVAL;
+    if (!device_memory(in, p.device) || !device_memory(out, p.device)) return SHTX_EINVAL;
+    return SHTX_OK;
+}
+
+}  // namespace shtx
+
+using shtx::check_args;
+using shtx::mark_done;
+using shtx::wait_done;
+
+namespace {
+
+int hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return SHTX_OK;
+    (void)hipGetLastError();
+    if (std::getenv("SHTX_DEBUG")) std::fprintf(stderr, "shtx: HIP error %d: %s\n", (int)e, hipGetErrorString(e));
+    return SHTX_EHIP;
+}
 
 // Launch the kernels of one transform kind on stream s.
 hipError_t launch_kind(Plan &p, int kind, const void *in, void *out, hipStream_t s, bool timed)
@@ -110,18 +131,6 @@ hipError_t launch_kind(Plan &p, int kind, const void *in, void *out, hipStream_t
     return e;
 }
 
-// Argument checks shared by every transform entry point.
-int check_args(const Plan &p, int kind, const void *in, const void *out)
-{
-    if (!in || !out || !p.shapes_ok) return SHTX_EINVAL;
-    bool spec_in = kind == shtx::kInverse || kind == shtx::kDirectAdj;
-    size_t nin = spec_in ? spec_bytes(p) : grid_bytes(p);
-    size_t nout = spec_in ? grid_bytes(p) : spec_bytes(p);
-    if (overlap(in, nin, out, nout)) return SHTX_EINVAL;
-    if (!aligned16(in) || !aligned16(out)) return SHTX_EINVAL;
-    if (!device_memory(in, p.device) || !device_memory(out, p.device)) return SHTX_EINVAL;
-    return SHTX_OK;
-}
 
 int run(shtx_plan h, int kind, const void *in, void *out, void *stream)
 {

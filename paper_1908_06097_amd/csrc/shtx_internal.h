@@ -180,6 +180,12 @@ struct Plan {
 // Element sizes.
 inline int grid_elem_bytes(int prec) { return prec == SHTX_FP64 ? 8 : 4; }
 
+// Transform-call helpers of the C ABI (capi.cpp): argument checks (SHTX_OK or
+// SHTX_EINVAL, nothing launched), and the per-plan completion event.
+int check_args(const Plan &p, int kind, const void *in, const void *out);
+hipError_t mark_done(Plan &p, hipStream_t s);
+hipError_t wait_done(Plan &p);
+
 // Kernel launchers (each checks its launch shape on the host first).
 hipError_t launch_gauss_nodes(int nlat, double *mu, double *w, hipStream_t s);
 hipError_t launch_legendre_tables(Plan &p, hipStream_t s);
@@ -266,3 +272,8 @@ std::vector<Item> layout_by_xcd(const std::vector<std::vector<Item>> &groups,
 }
 
 }  // namespace shtx
+
+// The opaque handle of the C ABI.
+struct shtx_plan_s {
+    shtx::Plan p;
+};
