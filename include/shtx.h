@@ -36,7 +36,12 @@
  * type): SHTX_FP64 plain double; SHTX_FP32 single precision on the matrix
  * cores with FP32 accumulation; SHTX_BF16X3 split bfloat16 hi+lo operands
  * (three products, lo*lo dropped) with per-m power-of-two scaling of the
- * Legendre table and FP32 accumulation.
+ * Legendre table and FP32 accumulation; SHTX_FP16X3 the same split with IEEE
+ * half hi+lo operands (11-bit halves, 5-bit exponent), the table block of
+ * each m scaled so that its largest entry lies in [2^13, 2^14) and each
+ * field's data operand scaled likewise from a bound on its largest value,
+ * so that both halves stay in half's normal range; the scales are powers of
+ * two and are undone exactly on the FP32 accumulators.
  *
  * Ownership and errors.  A plan owns its tables and workspace, allocated at
  * create time and freed at destroy; the transform calls allocate nothing.
@@ -64,7 +69,7 @@ extern "C" {
 typedef struct shtx_plan_s *shtx_plan;
 
 enum shtx_grid { SHTX_GRID_FULL = 0, SHTX_GRID_OCTAHEDRAL = 1 };
-enum shtx_prec { SHTX_FP64 = 0, SHTX_FP32 = 1, SHTX_BF16X3 = 2 };
+enum shtx_prec { SHTX_FP64 = 0, SHTX_FP32 = 1, SHTX_BF16X3 = 2, SHTX_FP16X3 = 3 };
 
 enum shtx_status {
     SHTX_OK = 0,

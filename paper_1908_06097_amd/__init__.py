@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libshtx.so")
 
 GRIDS = {"full": 0, "octahedral": 1}
-PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 FLAG_GRAPH = 1
 FLAG_TIMING = 2
 FLAG_AUTOTUNE = 4

@@ -131,8 +131,8 @@ int autotune_plan(Plan &p, hipStream_t s)
                 fail(arc);
                 break;
             }
-            double ti = time_ms(s, ea, eb, reps, [&] { return launch_gemm_inverse(p, spec, p.d_four, s); });
-            double td = time_ms(s, ea, eb, reps, [&] { return launch_gemm_direct(p, p.d_four, spec, false, s); });
+            double ti = time_ms(s, ea, eb, reps, [&] { return launch_gemm_inverse(p, spec, p.d_four, p.d_fmax, s); });
+            double td = time_ms(s, ea, eb, reps, [&] { return launch_gemm_direct(p, p.d_four, spec, false, p.d_fmax, s); });
             if (std::getenv("SHTX_DEBUG"))
                 std::fprintf(stderr, "shtx tune: GEMM %dx%d inverse %.3f ms direct %.3f ms\n", cbm[c], cbn[c], ti, td);
             if (ti >= 0 && ti < bi) {
@@ -161,7 +161,7 @@ int autotune_plan(Plan &p, hipStream_t s)
             }
             double tf = time_ms(s, ea, eb, reps, [&] {
                 hipError_t e = launch_fft_c2r(p, p.d_four, grid, false, s);
-                return e != hipSuccess ? e : launch_fft_r2c(p, grid, p.d_four, false, s);
+                return e != hipSuccess ? e : launch_fft_r2c(p, grid, p.d_four, false, p.d_fmax, s);
             });
             if (std::getenv("SHTX_DEBUG")) std::fprintf(stderr, "shtx tune: FFT cap %d c2r+r2c %.3f ms\n", cap, tf);
             if (tf >= 0 && tf < bf) {

@@ -110,20 +110,20 @@ hipError_t launch_kind(Plan &p, int kind, const void *in, void *out, hipStream_t
     };
     switch (kind) {
     case shtx::kInverse:
-        e = timed_launch(0, [&] { return shtx::launch_gemm_inverse(p, in, p.d_four, s); });
+        e = timed_launch(0, [&] { return shtx::launch_gemm_inverse(p, in, p.d_four, p.d_fmax, s); });
         if (e == hipSuccess) e = timed_launch(2, [&] { return shtx::launch_fft_c2r(p, p.d_four, out, false, s); });
         break;
     case shtx::kDirectAdj:
-        e = timed_launch(0, [&] { return shtx::launch_gemm_inverse(p, in, p.d_four, s); });
+        e = timed_launch(0, [&] { return shtx::launch_gemm_inverse(p, in, p.d_four, p.d_fmax, s); });
         if (e == hipSuccess) e = timed_launch(2, [&] { return shtx::launch_fft_c2r(p, p.d_four, out, true, s); });
         break;
     case shtx::kDirect:
-        e = timed_launch(3, [&] { return shtx::launch_fft_r2c(p, in, p.d_four, false, s); });
-        if (e == hipSuccess) e = timed_launch(1, [&] { return shtx::launch_gemm_direct(p, p.d_four, out, false, s); });
+        e = timed_launch(3, [&] { return shtx::launch_fft_r2c(p, in, p.d_four, false, p.d_fmax, s); });
+        if (e == hipSuccess) e = timed_launch(1, [&] { return shtx::launch_gemm_direct(p, p.d_four, out, false, p.d_fmax, s); });
         break;
     case shtx::kInverseAdj:
-        e = timed_launch(3, [&] { return shtx::launch_fft_r2c(p, in, p.d_four, true, s); });
-        if (e == hipSuccess) e = timed_launch(1, [&] { return shtx::launch_gemm_direct(p, p.d_four, out, true, s); });
+        e = timed_launch(3, [&] { return shtx::launch_fft_r2c(p, in, p.d_four, true, p.d_fmax, s); });
+        if (e == hipSuccess) e = timed_launch(1, [&] { return shtx::launch_gemm_direct(p, p.d_four, out, true, p.d_fmax, s); });
         break;
     default:
         e = hipErrorInvalidValue;
@@ -289,7 +289,7 @@ int shtx_plan_legendre(shtx_plan h, int m, double *out)
     std::vector<unsigned char> hi(cnt * el), lo;
     hipError_t e = hipMemcpy(hi.data(), (const char *)p.d_tab_rk + b.off_rk * el, cnt * el,
                              hipMemcpyDeviceToHost);
-    if (e == hipSuccess && p.prec == SHTX_BF16X3) {
+    if (e == hipSuccess && shtx::split_form(p.prec)) {
         lo.resize(cnt * el);
         e = hipMemcpy(lo.data(), (const char *)p.d_tab_rk_lo + b.off_rk * el, cnt * el,
                       hipMemcpyDeviceToHost);
@@ -298,7 +298,8 @@ int shtx_plan_legendre(shtx_plan h, int m, double *out)
     auto val = [&](size_t idx) -> double {
         if (p.prec == SHTX_FP64) return reinterpret_cast<const double *>(hi.data())[idx];
         if (p.prec == SHTX_FP32) return reinterpret_cast<const float *>(hi.data())[idx];
-        auto bf = [](uint16_t u) {
+        auto bf = [&](uint16_t u) {
+            if (p.prec == SHTX_FP16X3) return (double)__builtin_bit_cast(_Float16, u);
             uint32_t x = (uint32_t)u << 16;
             float f;
             std::memcpy(&f, &x, 4);

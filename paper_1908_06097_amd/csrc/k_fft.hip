@@ -117,6 +117,11 @@ struct FftArgs {
     int nfld;
     int adjoint;
     int64_t npts;
+    // r2c only, when not null: per field, the largest magnitude of the
+    // Fourier values written (float bits, atomic max), collected per block in
+    // nf words of LDS at byte offset fmax_lds
+    unsigned *fmax;
+    int fmax_lds;
 };
 
 // exp(-2 pi i t / R) for the odd prime radices (t taken mod R), as
@@ -856,6 +861,10 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
     const unsigned npts = (unsigned)a.npts;
     const T *gridb = (const T *)a.in + (uint64_t)f0 * npts + d.grid_off;  // field f at gridb + f npts
     const int buf_off = 0;
+    __attribute__((address_space(3))) unsigned *smax =
+        (__attribute__((address_space(3))) unsigned *)((LdsByte *)fft_smem + a.fmax_lds);
+    if (a.fmax)
+        for (int f = threadIdx.x; f < nf; f += kFftThreads) smax[f] = 0u;  // ordered by the barrier below
 
     // 1. z_k = g_{2k} + i g_{2k+1}; Bluestein: times the chirp, zero-padded to L
     const int span = d.blue ? d.L : h;
@@ -948,7 +957,14 @@ __global__ __launch_bounds__(kFftThreads, 2) void k_fft_r2c(FftArgs a)
             T fac = (a.adjoint && m > 0) ? T(2) : T(1);
             y = {y.x * scale * fac, m == 0 ? T(0) : y.y * scale * fac};
             fourb[(unsigned)m * nfld + (unsigned)f] = y;
+            if (a.fmax)
+                __hip_atomic_fetch_max(smax + f, __float_as_uint((float)fmax(fabs(y.x), fabs(y.y))),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
+    }
+    if (a.fmax) {
+        __syncthreads();
+        for (int f = threadIdx.x; f < nf; f += kFftThreads) atomicMax(a.fmax + f0 + f, smax[f]);
     }
 }
 
@@ -1015,6 +1031,12 @@ bool check_fft(const Plan &p, int cap)
             SHTX_FFT_FAIL;
         if (prod != d.L) SHTX_FFT_FAIL;
     }
+    if (p.prec == SHTX_FP16X3) {
+        // the r2c kernel's per-field maxima sit after the block's LDS
+        for (const RingDesc &d : p.rings)
+            if (d.fb > kFmaxFields) SHTX_FFT_FAIL;
+        if (p.fft_lds_bytes + 4 * kFmaxFields > 160 * 1024) SHTX_FFT_FAIL;
+    }
     for (const FftItem &it : p.fft_items) {
         if (it.ring < 0) continue;
         if (it.ring >= p.nlat || it.f0 < 0 || it.nf < 1 || it.f0 + it.nf > p.nfld) SHTX_FFT_FAIL;
@@ -1024,15 +1046,42 @@ bool check_fft(const Plan &p, int cap)
 #undef SHTX_FFT_FAIL
 }
 
+__global__ void k_zero_u32(unsigned *x, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0u;
+}
+
+// LDS words the r2c kernel adds for the per-field maxima: the largest
+// fields-per-block of the plan.
+int fmax_lds_bytes(const Plan &p)
+{
+    int fb = 0;
+    for (const RingDesc &d : p.rings) fb = std::max(fb, d.fb);
+    return 4 * fb;
+}
+
 template <typename T, int CAP, bool C2R>
-hipError_t launch_fft(const Plan &p, const void *in, void *out, bool adjoint, hipStream_t s)
+hipError_t launch_fft(const Plan &p, const void *in, void *out, bool adjoint, unsigned *fmax, hipStream_t s)
 {
     // the rings, passes and work list were checked against the kernels'
     // limits (check_fft) when the plan's blocking was built
     if (!p.shapes_ok || p.fft_items.empty()) return hipErrorInvalidValue;
-    FftArgs a{p.d_rings, p.d_fft_items, p.d_passes, p.d_twid, in, out, p.nfld, adjoint ? 1 : 0, p.npts};
+    FftArgs a{p.d_rings, p.d_fft_items, p.d_passes, p.d_twid, in, out, p.nfld, adjoint ? 1 : 0, p.npts,
+              nullptr, p.fft_lds_bytes};
+    int lds = p.fft_lds_bytes;
+    if (!C2R && p.prec == SHTX_FP16X3) {
+        // per-field maxima of the Fourier workspace for the split-half GEMM:
+        // cleared here (a kernel, not a memset, so that graph replays clear it)
+        if (!fmax) return hipErrorInvalidValue;
+        k_zero_u32<<<(p.nfld + 255) / 256, 256, 0, s>>>(fmax, p.nfld);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        a.fmax = fmax;
+        lds += fmax_lds_bytes(p);
+    }
     auto kern = C2R ? k_fft_c2r<T, CAP> : k_fft_r2c<T, CAP>;
-    kern<<<(int)p.fft_items.size(), kFftThreads, p.fft_lds_bytes, s>>>(a);
+    kern<<<(int)p.fft_items.size(), kFftThreads, lds, s>>>(a);
     return hipGetLastError();
 }
 
@@ -1069,14 +1118,14 @@ bool fft_shapes_ok(const Plan &p)
 
 hipError_t launch_fft_c2r(const Plan &p, const void *four, void *grid, bool adjoint, hipStream_t s)
 {
-    if (p.prec == SHTX_FP64) return launch_fft<double, kFftCapF64, true>(p, four, grid, adjoint, s);
-    return launch_fft<float, kFftCapF32, true>(p, four, grid, adjoint, s);
+    if (p.prec == SHTX_FP64) return launch_fft<double, kFftCapF64, true>(p, four, grid, adjoint, nullptr, s);
+    return launch_fft<float, kFftCapF32, true>(p, four, grid, adjoint, nullptr, s);
 }
 
-hipError_t launch_fft_r2c(const Plan &p, const void *grid, void *four, bool adjoint, hipStream_t s)
+hipError_t launch_fft_r2c(const Plan &p, const void *grid, void *four, bool adjoint, unsigned *fmax, hipStream_t s)
 {
-    if (p.prec == SHTX_FP64) return launch_fft<double, kFftCapF64, false>(p, grid, four, adjoint, s);
-    return launch_fft<float, kFftCapF32, false>(p, grid, four, adjoint, s);
+    if (p.prec == SHTX_FP64) return launch_fft<double, kFftCapF64, false>(p, grid, four, adjoint, nullptr, s);
+    return launch_fft<float, kFftCapF32, false>(p, grid, four, adjoint, fmax, s);
 }
 
 }  // namespace shtx

@@ -75,6 +75,11 @@ struct GemmArgs {
     int trunc, nlat, nfld;
     int adjoint;
     int64_t nspec;
+    // split IEEE-half form: per-field largest magnitude of the data source
+    // (float bits) and the factor that turns it into a bound on the data
+    // operand's entries
+    const unsigned *fmax;
+    float dbound;
 };
 
 __device__ inline int64_t spec_base(int trunc, int m) { return (int64_t)m * (2 * trunc + 3 - m) / 2; }
@@ -393,38 +398,89 @@ __global__ __launch_bounds__(64 * NW, 2) void k_leg_mfma(GemmArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Split BF16 (hi + lo) with FP32 accumulation: 3 MFMAs per tile product
-// (hi*hi + hi*lo + lo*hi).  16x16x32 MFMA: lane l supplies A[l%16][8(l/16)..+7]
-// and B[8(l/16)..+7][l%16]; LDS tiles are row-major with kappa contiguous:
-// As[p][h][i][kappa], Bs[p][h][j][kappa] (h = hi, lo).
+// Split half precision with FP32 accumulation: each operand is a sum hi + lo
+// of two bfloat16 or two IEEE-half values, and a tile product is three MFMAs
+// (hi*lo + lo*hi + hi*hi; lo*lo is dropped).  16x16x32 MFMA: lane l supplies
+// A[l%16][8(l/16)..+7] and B[8(l/16)..+7][l%16]; LDS tiles are row-major
+// with kappa contiguous: As[p][h][i][kappa], Bs[p][h][j][kappa] (h = hi, lo).
+//
+// The table is stored already split, scaled by 2^e_m per m.  The data
+// operand is split here, once per block and stage, with the packed
+// round-to-nearest-even conversions of gfx950.  IEEE half has a 5-bit
+// exponent, so its data operand is also scaled per field by 2^E_f, chosen
+// from a bound on the field's largest value; bfloat16 has the FP32 exponent
+// range and needs no data scale.
 // ---------------------------------------------------------------------------
-__device__ inline unsigned short bf16_rne(float f)
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+// two complex values at an 8-byte aligned address, one 16-byte load (vector
+// memory instructions need only 4-byte alignment)
+typedef float f32x4a8 __attribute__((ext_vector_type(4), aligned(8)));
+
+template <bool F16>
+__device__ inline void split2(float x0, float x1, unsigned &hi, unsigned &lo)
 {
-    unsigned u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+    if constexpr (F16) {
+        const f16x2 h = {(_Float16)x0, (_Float16)x1};
+        const f16x2 l = {(_Float16)(x0 - (float)h[0]), (_Float16)(x1 - (float)h[1])};
+        hi = __builtin_bit_cast(unsigned, h);
+        lo = __builtin_bit_cast(unsigned, l);
+    } else {
+        const bf16x2 h = {(__bf16)x0, (__bf16)x1};
+        const bf16x2 l = {(__bf16)(x0 - (float)h[0]), (__bf16)(x1 - (float)h[1])};
+        hi = __builtin_bit_cast(unsigned, h);
+        lo = __builtin_bit_cast(unsigned, l);
+    }
 }
-__device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 
-__device__ inline void split_bf16(float x, unsigned short &hi, unsigned short &lo)
+// eight floats -> one 16-byte word of hi halves and one of lo halves
+template <bool F16>
+__device__ inline void split8(const float *x, u32x4 &hi, u32x4 &lo)
 {
-    hi = bf16_rne(x);
-    lo = bf16_rne(x - bf16_to_f(hi));
+    unsigned h[4], l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) split2<F16>(x[2 * i], x[2 * i + 1], h[i], l[i]);
+    hi = u32x4{h[0], h[1], h[2], h[3]};
+    lo = u32x4{l[0], l[1], l[2], l[3]};
 }
 
+template <bool F16>
+__device__ inline f32x4 mfma_split(u32x4 a, u32x4 b, f32x4 c)
+{
+    if constexpr (F16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                       c, 0, 0, 0);
+}
 
-template <int BM, int BN, int BK, bool INVERSE>
-__global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
+// Exponent E_f of field f's data operand in the half form: with the field's
+// largest magnitude times `bound` (a bound on the operand's entries) equal to
+// x 2^X, x in [1/2, 1), E_f = 14 - X puts the bound in [2^13, 2^14); 0 for an
+// all-zero field.
+__device__ inline int field_exp(const unsigned *fmax, int f, float bound)
+{
+    const float mx = __uint_as_float(fmax[f]) * bound;
+    if (!(mx > 0.f)) return 0;
+    int X;
+    (void)frexpf(mx, &X);
+    return 14 - X;
+}
+
+template <bool F16, int BM, int BN, int BK, bool INVERSE>
+__global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
 {
     constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
     constexpr int LDK = BK + 8;  // 16-byte aligned rows, staggered banks
     constexpr int CH = BK / 8;   // 16-byte chunks per tile row
     constexpr int NA = (2 * 2 * BM * CH) / 256;  // table chunk loads per thread
-    // operand units per thread: INV (field, parity, 8 consecutive k),
-    // DIR (field, 8 consecutive rings)
-    constexpr int NU = INVERSE ? (BN / 2) * 2 * (BK / 8) / 256 : (BN / 2) * (BK / 8) / 256;
+    // operand units: INV (field, 16 consecutive n = 8 k of each parity),
+    // DIR (field, 8 consecutive rings, north and south)
+    constexpr int NUNIT = (BN / 2) * CH;
+    constexpr int NU = (NUNIT + 255) / 256;
     static_assert(NA * 256 == 2 * 2 * BM * CH, "table tile must split evenly");
-    static_assert(NU >= 1, "operand tile too small");
     // operand tiles As[p][h][i][kappa], Bs[p][h][j][kappa]; the direct form
     // reuses the same LDS to stage its output tile
     constexpr int NSMEM16 = 2 * 2 * (BM + BN) * LDK;
@@ -451,8 +507,24 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
     const int kend = INVERSE ? b.K0 : b.R;
     const int nstages = (kend + BK - 1) / BK;
 
+    // each thread's operand units keep their field over all stages
+    int ufl[NU];
+    bool uon[NU];
+    float usc[NU];  // data scale 2^E_f (half form)
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int idx = tid + u * 256;
+        ufl[u] = INVERSE ? idx / CH : idx % (BN / 2);
+        uon[u] = idx < NUNIT;
+        usc[u] = 1.f;
+        if constexpr (F16) {
+            const int f = col0 / 2 + ufl[u];
+            if (uon[u] && f < a.nfld) usc[u] = ldexpf(1.f, field_exp(a.fmax, f, a.dbound));
+        }
+    }
+
     u32x4 ra[NA];
-    float2 rv[NU][INVERSE ? 8 : 16];
+    float2 rv[NU][16];
     // DIR: Fourier offsets and weights of each unit's 8 rings, fetched one
     // stage ahead of the data so that no data load waits on them
     constexpr int NMU = INVERSE ? 1 : NU, NMQ = INVERSE ? 1 : 8;
@@ -462,12 +534,15 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
 #pragma unroll
         for (int u = 0; u < NMU; ++u) {
             int rc = (tid + u * 256) / (BN / 2);
+            // with 64 fields per tile a unit's rings are uniform over a wave:
+            // scalar loads into scalar registers
+            if constexpr (BN / 2 == 64) rc = __builtin_amdgcn_readfirstlane(rc);
 #pragma unroll
             for (int q = 0; q < NMQ; ++q) {
                 int r = kk + rc * 8 + q;
                 RingPair o = {-1, -1};
                 float w = 0.f;
-                if (r < b.R) {
+                if ((BN / 2 == 64 || uon[u]) && r < b.R) {
                     o = a.ring_pair[b.j0 + r];
                     w = a.adjoint ? 1.f : ((const float *)a.ring_q)[b.j0 + r];
                 }
@@ -485,33 +560,38 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
             int hl = rem / (BM * CH);
             rem -= hl * BM * CH;
             int i = rem / CH, ch = rem - i * CH;
-            ra[v] = *reinterpret_cast<const u32x4 *>((hl ? Tl : Th) + p * pstride + (int64_t)(row0 + i) * lda + kk + ch * 8);
+            ra[v] = *reinterpret_cast<const u32x4 *>((hl ? Tl : Th) + p * pstride + (int64_t)(row0 + i) * lda + kk +
+                                                     ch * 8);
         }
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
-            int idx = tid + u * 256;
+            const int idx = tid + u * 256;
+            const float2 zero = {0.f, 0.f};
             if (INVERSE) {
-                // 8 consecutive k of one parity of one field: n = m + 2(kk + q) + p
-                int fl = idx / (2 * (BK / 8)), rem = idx - fl * 2 * (BK / 8);
-                int p = rem & 1, qc = rem >> 1;
-                int f = col0 / 2 + fl;
-                const float2 *spec = (const float2 *)a.in + (int64_t)f * a.nspec + sb;
+                // 16 consecutive n = m + 2 kk + 16 qc + t of one field: parity t & 1, k = kk + 8 qc + t / 2
+                const int qc = idx % CH, f = col0 / 2 + ufl[u];
+                const int nrel0 = 2 * kk + 16 * qc;
+                const float2 *src = (const float2 *)a.in + (int64_t)f * a.nspec + sb + nrel0;
+                if (uon[u] && f < a.nfld && m + nrel0 + 15 <= a.trunc) {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    int nrel = 2 * (kk + qc * 8 + q) + p;
-                    float2 z = {0.f, 0.f};
-                    if (f < a.nfld && m + nrel <= a.trunc) z = spec[nrel];
-                    rv[u][q] = z;
+                    for (int t = 0; t < 8; ++t) {
+                        const f32x4a8 v4 = *reinterpret_cast<const f32x4a8 *>(src + 2 * t);
+                        rv[u][2 * t] = float2{v4[0], v4[1]};
+                        rv[u][2 * t + 1] = float2{v4[2], v4[3]};
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 16; ++t)
+                        rv[u][t] = (uon[u] && f < a.nfld && m + nrel0 + t <= a.trunc) ? src[t] : zero;
                 }
             } else {
                 // 8 consecutive rings of one field, north and south; the
                 // rings' offsets come from the previous stage's meta fetch
-                int rc = idx / (BN / 2), cp = idx - rc * (BN / 2);
-                int f = col0 / 2 + cp;
+                const int f = col0 / 2 + ufl[u];
                 const float2 *four = (const float2 *)a.in;
 #pragma unroll
                 for (int q = 0; q < 8; ++q) {
-                    float2 gn = {0.f, 0.f}, gs = {0.f, 0.f};
+                    float2 gn = zero, gs = zero;
                     if (mp1[u][q].n >= 0 && f < a.nfld) {
                         gn = four[((int64_t)mp1[u][q].n + m) * a.nfld + f];
                         gs = four[((int64_t)mp1[u][q].s + m) * a.nfld + f];
@@ -521,24 +601,6 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
                 }
             }
         }
-    };
-    // pack 8 floats into (hi, lo) bf16 halves, one 16-byte word each
-    auto pack2 = [](float x0, float x1, unsigned &hi, unsigned &lo) {
-        unsigned short h0, l0, h1, l1;
-        split_bf16(x0, h0, l0);
-        split_bf16(x1, h1, l1);
-        hi = h0 | (unsigned)h1 << 16;
-        lo = l0 | (unsigned)l1 << 16;
-    };
-    auto split8 = [&](float x0, float x1, float x2, float x3, float x4, float x5, float x6, float x7,
-                      u32x4 &hi, u32x4 &lo) {
-        unsigned h0, l0, h1, l1, h2, l2, h3, l3;
-        pack2(x0, x1, h0, l0);
-        pack2(x2, x3, h1, l1);
-        pack2(x4, x5, h2, l2);
-        pack2(x6, x7, h3, l3);
-        hi = u32x4{h0, h1, h2, h3};
-        lo = u32x4{l0, l1, l2, l3};
     };
     auto store = [&]() __attribute__((always_inline)) {
 #pragma unroll
@@ -552,49 +614,44 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
         }
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
-            int idx = tid + u * 256;
+            if (!uon[u]) continue;
+            const int idx = tid + u * 256;
+            const float sc = usc[u];
+            float x[8];
             u32x4 hi, lo;
             if (INVERSE) {
-                int fl = idx / (2 * (BK / 8)), rem = idx - fl * 2 * (BK / 8);
-                int p = rem & 1, qc = rem >> 1;
-                if (m == 0) {
+                const int fl = ufl[u], qc = idx % CH;
 #pragma unroll
-                    for (int q = 0; q < 8; ++q) rv[u][q].y = 0.f;
+                for (int p = 0; p < 2; ++p) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) x[q] = rv[u][2 * q + p].x * sc;
+                    split8<F16>(x, hi, lo);
+                    *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * fl][qc * 8]) = hi;
+                    *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * fl][qc * 8]) = lo;
+                    // Im a^0_n is ignored
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) x[q] = m == 0 ? 0.f : rv[u][2 * q + p].y * sc;
+                    split8<F16>(x, hi, lo);
+                    *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * fl + 1][qc * 8]) = hi;
+                    *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * fl + 1][qc * 8]) = lo;
                 }
-#define z rv[u]
-                split8(z[0].x, z[1].x, z[2].x, z[3].x, z[4].x, z[5].x, z[6].x, z[7].x, hi, lo);
-                *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * fl][qc * 8]) = hi;
-                *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * fl][qc * 8]) = lo;
-                split8(z[0].y, z[1].y, z[2].y, z[3].y, z[4].y, z[5].y, z[6].y, z[7].y, hi, lo);
-                *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * fl + 1][qc * 8]) = hi;
-                *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * fl + 1][qc * 8]) = lo;
-#undef z
             } else {
-                int rc = idx / (BN / 2), cp = idx - rc * (BN / 2);
+                // hemispheric fold: parity 0 takes q (north + south), parity 1 q (north - south)
+                const int cp = ufl[u], rc = idx / (BN / 2);
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const float w = mq1[u][q];
-                    rv[u][2 * q] = float2{w * rv[u][2 * q].x, w * rv[u][2 * q].y};
-                    rv[u][2 * q + 1] = float2{w * rv[u][2 * q + 1].x, w * rv[u][2 * q + 1].y};
+                for (int p = 0; p < 2; ++p) {
+                    const float sg = p ? -1.f : 1.f;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) x[q] = (mq1[u][q] * sc) * (rv[u][2 * q].x + sg * rv[u][2 * q + 1].x);
+                    split8<F16>(x, hi, lo);
+                    *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * cp][rc * 8]) = hi;
+                    *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * cp][rc * 8]) = lo;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) x[q] = (mq1[u][q] * sc) * (rv[u][2 * q].y + sg * rv[u][2 * q + 1].y);
+                    split8<F16>(x, hi, lo);
+                    *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * cp + 1][rc * 8]) = hi;
+                    *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * cp + 1][rc * 8]) = lo;
                 }
-#define z rv[u]  // z[2q] north, z[2q+1] south of ring q
-#define SHTX_FOLD(c, sgn)                                                                         \
-    split8(z[0].c sgn z[1].c, z[2].c sgn z[3].c, z[4].c sgn z[5].c, z[6].c sgn z[7].c,              \
-           z[8].c sgn z[9].c, z[10].c sgn z[11].c, z[12].c sgn z[13].c, z[14].c sgn z[15].c, hi, lo)
-                SHTX_FOLD(x, +);
-                *reinterpret_cast<u32x4 *>(&Bs[0][0][2 * cp][rc * 8]) = hi;
-                *reinterpret_cast<u32x4 *>(&Bs[0][1][2 * cp][rc * 8]) = lo;
-                SHTX_FOLD(y, +);
-                *reinterpret_cast<u32x4 *>(&Bs[0][0][2 * cp + 1][rc * 8]) = hi;
-                *reinterpret_cast<u32x4 *>(&Bs[0][1][2 * cp + 1][rc * 8]) = lo;
-                SHTX_FOLD(x, -);
-                *reinterpret_cast<u32x4 *>(&Bs[1][0][2 * cp][rc * 8]) = hi;
-                *reinterpret_cast<u32x4 *>(&Bs[1][1][2 * cp][rc * 8]) = lo;
-                SHTX_FOLD(y, -);
-                *reinterpret_cast<u32x4 *>(&Bs[1][0][2 * cp + 1][rc * 8]) = hi;
-                *reinterpret_cast<u32x4 *>(&Bs[1][1][2 * cp + 1][rc * 8]) = lo;
-#undef SHTX_FOLD
-#undef z
             }
         }
     };
@@ -606,6 +663,12 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
         for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int j = 0; j < FN; ++j) acc[p][i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // a wave whose whole sub-tile lies past the valid rows or columns (the
+    // ragged edge of an m block or of the field range) still loads and
+    // stores its share of the operand tiles but skips the MFMAs
+    const bool mfma_on = __builtin_amdgcn_readfirstlane(
+        (row0 + wr < (INVERSE ? b.R : b.K0) && col0 + wc < ncol) ? 1 : 0);
 
     if (!INVERSE) meta(0, mp1, mq1);
     load(0);
@@ -624,40 +687,51 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
         __syncthreads();
         if (s + 1 < nstages) load((s + 1) * BK);  // in flight during the MFMAs
         if (!INVERSE && s + 2 < nstages) meta((s + 2) * BK, mp2, mq2);
+        if (mfma_on) {
 #pragma unroll
-        for (int q = 0; q < BK; q += 32) {
-            const int kq = q + 8 * (lane >> 4);
+            for (int q = 0; q < BK; q += 32) {
+                const int kq = q + 8 * (lane >> 4);
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                bf16x8 ah[FM], al[FM], bh[FN], bl[FN];
+                for (int p = 0; p < 2; ++p) {
+                    u32x4 ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
-                for (int i = 0; i < FM; ++i) {
-                    const int ai = wr + i * 16 + (lane & 15);
-                    ah[i] = *reinterpret_cast<const bf16x8 *>(&As[p][0][ai][kq]);
-                    al[i] = *reinterpret_cast<const bf16x8 *>(&As[p][1][ai][kq]);
-                }
-#pragma unroll
-                for (int j = 0; j < FN; ++j) {
-                    const int bj = wc + j * 16 + (lane & 15);
-                    bh[j] = *reinterpret_cast<const bf16x8 *>(&Bs[p][0][bj][kq]);
-                    bl[j] = *reinterpret_cast<const bf16x8 *>(&Bs[p][1][bj][kq]);
-                }
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
+                    for (int i = 0; i < FM; ++i) {
+                        const int ai = wr + i * 16 + (lane & 15);
+                        ah[i] = *reinterpret_cast<const u32x4 *>(&As[p][0][ai][kq]);
+                        al[i] = *reinterpret_cast<const u32x4 *>(&As[p][1][ai][kq]);
+                    }
 #pragma unroll
                     for (int j = 0; j < FN; ++j) {
-                        f32x4 c = acc[p][i][j];
-                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], c, 0, 0, 0);
-                        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], c, 0, 0, 0);
-                        acc[p][i][j] = c;
+                        const int bj = wc + j * 16 + (lane & 15);
+                        bh[j] = *reinterpret_cast<const u32x4 *>(&Bs[p][0][bj][kq]);
+                        bl[j] = *reinterpret_cast<const u32x4 *>(&Bs[p][1][bj][kq]);
                     }
+#pragma unroll
+                    for (int i = 0; i < FM; ++i)
+#pragma unroll
+                        for (int j = 0; j < FN; ++j) {
+                            f32x4 c = acc[p][i][j];
+                            c = mfma_split<F16>(ah[i], bl[j], c);
+                            c = mfma_split<F16>(al[i], bh[j], c);
+                            c = mfma_split<F16>(ah[i], bh[j], c);
+                            acc[p][i][j] = c;
+                        }
+                }
             }
         }
         __syncthreads();
     }
 
-    const float unscale = ldexpf(1.f, -b.e);
+    // unscaling exponent of each of the lane's columns: e_m (+ E_f)
+    int eu[FN];
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        eu[j] = b.e;
+        if constexpr (F16) {
+            const int c = col0 + wc + j * 16 + (lane & 15);
+            if (c < ncol) eu[j] += field_exp(a.fmax, c >> 1, a.dbound);
+        }
+    }
     if (INVERSE) {
         float *four = (float *)a.out;
         RingPair ro[FM][4];
@@ -679,8 +753,8 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
                     int c = col0 + wc + j * 16 + (lane & 15);
                     if (o.n >= 0 && c < ncol) {
                         float s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
-                        four[2 * ((int64_t)o.n + m) * a.nfld + c] = (s0 + s1) * unscale;
-                        four[2 * ((int64_t)o.s + m) * a.nfld + c] = (s0 - s1) * unscale;
+                        four[2 * ((int64_t)o.n + m) * a.nfld + c] = ldexpf(s0 + s1, -eu[j]);
+                        four[2 * ((int64_t)o.s + m) * a.nfld + c] = ldexpf(s0 - s1, -eu[j]);
                     }
                 }
     } else {
@@ -706,7 +780,7 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
                             for (int v = 0; v < 4; ++v) {
                                 const int k = wr + i * 16 + 4 * (lane >> 4) + v;
                                 const int cl = j * 16 + (lane & 15);
-                                float val = acc[p][i][j][v] * unscale;
+                                float val = ldexpf(acc[p][i][j][v], -eu[j]);
                                 if (m == 0 && (cl & 1)) val = 0.f;
                                 st[((cl >> 1) * RS + p + 2 * k) * 2 + (cl & 1)] = val;
                             }
@@ -724,7 +798,7 @@ __global__ __launch_bounds__(256) void k_leg_bf16x3(GemmArgs a)
     }
 }
 
-GemmArgs make_args(const Plan &p, bool inverse_shape, const void *in, void *out, bool adjoint)
+GemmArgs make_args(const Plan &p, bool inverse_shape, const void *in, void *out, bool adjoint, unsigned *fmax)
 {
     GemmArgs a{};
     a.mb = p.d_mb;
@@ -738,13 +812,18 @@ GemmArgs make_args(const Plan &p, bool inverse_shape, const void *in, void *out,
     a.nfld = p.nfld;
     a.adjoint = adjoint ? 1 : 0;
     a.nspec = p.nspec;
-    if (p.prec == SHTX_BF16X3) {
+    if (split_form(p.prec)) {
         a.tab = inverse_shape ? p.d_tab_rk : p.d_tab_kr;
         a.tab_lo = inverse_shape ? p.d_tab_rk_lo : p.d_tab_kr_lo;
     } else {
         a.tab = inverse_shape ? p.d_tab_kr : p.d_tab_rk;
         a.tab_lo = nullptr;
     }
+    // the inverse-shaped launch splits spectral coefficients (bounded by the
+    // field maximum itself); the direct-shaped one splits q_r (G_north +-
+    // G_south), bounded by 2 max_r q_r times the largest Fourier value
+    a.fmax = fmax;
+    a.dbound = inverse_shape ? 1.f : (float)(2.0 * (adjoint ? 1.0 : p.qmax));
     return a;
 }
 
@@ -826,16 +905,41 @@ hipError_t launch_mfma(const Plan &p, const GemmArgs &a, int bm, int bn, hipStre
     return launch_mfma_part<T, BK, INV>(a, nmain, (int)items.size() - nmain, bm, tail_bn, s);
 }
 
-template <bool INV>
-hipError_t launch_bf16(const Plan &p, const GemmArgs &a, int bm, int bn, hipStream_t s)
+// Largest magnitude of each field's spectral coefficients (Re and Im of
+// every a_n^m except Im a_n^0, which the transforms ignore), as float bits,
+// one block per field: the bound from which the half form scales the
+// inverse-shaped GEMM's data operand.
+__global__ __launch_bounds__(1024) void k_spec_absmax(const float2 *spec, int64_t nspec, int trunc, unsigned *fmax)
+{
+    __shared__ float red[16];
+    const int f = blockIdx.x;
+    const float2 *row = spec + (int64_t)f * nspec;
+    float mx = 0.f;
+    for (int64_t i = threadIdx.x; i < nspec; i += 1024) {
+        const float2 z = row[i];
+        mx = fmaxf(mx, fabsf(z.x));
+        if (i > trunc) mx = fmaxf(mx, fabsf(z.y));  // index i <= N is m = 0
+    }
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float t = 0.f;
+        for (int w = 0; w < 16; ++w) t = fmaxf(t, red[w]);
+        fmax[f] = __float_as_uint(t);
+    }
+}
+
+template <bool F16, bool INV>
+hipError_t launch_split(const Plan &p, const GemmArgs &a, int bm, int bn, hipStream_t s)
 {
     const std::vector<GemmItem> &items = INV ? p.inv_items : p.dir_items;
     const int grid = (int)items.size();
     if (!p.shapes_ok || grid < 1) return hipErrorInvalidValue;
     if (bm == 128 && bn == 128)
-        k_leg_bf16x3<128, 128, 32, INV><<<grid, 256, 0, s>>>(a);
+        k_leg_split<F16, 128, 128, 32, INV><<<grid, 256, 0, s>>>(a);
     else if (bm == 64 && bn == 128)
-        k_leg_bf16x3<64, 128, 32, INV><<<grid, 256, 0, s>>>(a);
+        k_leg_split<F16, 64, 128, 32, INV><<<grid, 256, 0, s>>>(a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -850,7 +954,7 @@ int gemm_tile_candidates(int prec, int *bm, int *bn, int max)
     static const int f64[][2] = {{64, 64}, {32, 64}, {64, 32}};
     static const int b16[][2] = {{128, 128}, {64, 128}};
     const int(*t)[2] = prec == SHTX_FP64 ? f64 : prec == SHTX_FP32 ? f32 : b16;
-    int n = prec == SHTX_BF16X3 ? 2 : 3;
+    int n = split_form(prec) ? 2 : 3;
     for (int i = 0; i < n && i < max; ++i) {
         bm[i] = t[i][0];
         bn[i] = t[i][1];
@@ -869,7 +973,7 @@ bool gemm_tile_supported(int prec, int bm, int bn)
 
 bool gemm_shapes_ok(const Plan &p)
 {
-    int bk = p.prec == SHTX_BF16X3 ? 32 : 16;
+    int bk = split_form(p.prec) ? 32 : 16;
     if (!gemm_tile_supported(p.prec, p.inv_bm, p.inv_bn) || !gemm_tile_supported(p.prec, p.dir_bm, p.dir_bn))
         return false;
     bool inv_ok = p.inv_items.empty() ||
@@ -877,21 +981,34 @@ bool gemm_shapes_ok(const Plan &p)
     return inv_ok && check_work_list(p, p.dir_items, p.dir_nmain, false, p.dir_bm, p.dir_bn, p.dir_tail_bn, bk);
 }
 
-hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, hipStream_t s)
+hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, unsigned *fmax, hipStream_t s)
 {
-    GemmArgs a = make_args(p, true, spec, four, false);
+    GemmArgs a = make_args(p, true, spec, four, false, fmax);
     if (p.inv_items.empty()) return hipSuccess;
     if (p.prec == SHTX_FP64) return launch_mfma<double, 16, true>(p, a, p.inv_bm, p.inv_bn, s);
     if (p.prec == SHTX_FP32) return launch_mfma<float, 16, true>(p, a, p.inv_bm, p.inv_bn, s);
-    return launch_bf16<true>(p, a, p.inv_bm, p.inv_bn, s);
+    if (p.prec == SHTX_FP16X3) {
+        if (!fmax) return hipErrorInvalidValue;
+        k_spec_absmax<<<p.nfld, 1024, 0, s>>>((const float2 *)spec, p.nspec, p.trunc, fmax);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return launch_split<true, true>(p, a, p.inv_bm, p.inv_bn, s);
+    }
+    return launch_split<false, true>(p, a, p.inv_bm, p.inv_bn, s);
 }
 
-hipError_t launch_gemm_direct(const Plan &p, const void *four, void *spec, bool adjoint, hipStream_t s)
+hipError_t launch_gemm_direct(const Plan &p, const void *four, void *spec, bool adjoint, unsigned *fmax,
+                              hipStream_t s)
 {
-    GemmArgs a = make_args(p, false, four, spec, adjoint);
+    GemmArgs a = make_args(p, false, four, spec, adjoint, fmax);
     if (p.prec == SHTX_FP64) return launch_mfma<double, 16, false>(p, a, p.dir_bm, p.dir_bn, s);
     if (p.prec == SHTX_FP32) return launch_mfma<float, 16, false>(p, a, p.dir_bm, p.dir_bn, s);
-    return launch_bf16<false>(p, a, p.dir_bm, p.dir_bn, s);
+    if (p.prec == SHTX_FP16X3) {
+        // the ring r2c FFT that wrote the workspace recorded each field's maximum
+        if (!fmax) return hipErrorInvalidValue;
+        return launch_split<true, false>(p, a, p.dir_bm, p.dir_bn, s);
+    }
+    return launch_split<false, false>(p, a, p.dir_bm, p.dir_bn, s);
 }
 
 }  // namespace shtx

@@ -177,8 +177,12 @@ __device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float((un
 
 // Column recurrence over n for one (m, ring).  MODE 0: per-m max |P̄| only;
 // MODE 1: store FP64; MODE 2: store FP32; MODE 3: store split BF16 hi + lo
-// scaled by 2^e_m.  Both table layouts are written: kr = [p][k][r] and
-// rk = [p][r][k] (k = (n - m - p) / 2).
+// scaled by 2^e_m, e_m putting the block's largest entry in [1/2, 1); MODE 4:
+// store split IEEE half hi + lo scaled by 2^e_m, the largest entry in
+// [2^13, 2^14) (half's 5-bit exponent: entries that small relative to the
+// block's largest lose their lo half to the subnormal range, a loss relative
+// to that largest entry of at most 2^-38).  Both table layouts are written:
+// kr = [p][k][r] and rk = [p][r][k] (k = (n - m - p) / 2).
 template <int MODE>
 __global__ void k_legendre_table(int trunc, const double *mu, const double *diag, MBlock *mbs,
                                  unsigned long long *mmax, void *tab_kr, void *tab_rk,
@@ -187,22 +191,23 @@ __global__ void k_legendre_table(int trunc, const double *mu, const double *diag
     const int m = blockIdx.y;
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     const MBlock b = mbs[m];
-    if (MODE == 3 && r == 0 && blockIdx.x == 0) {
-        // exponent: max * 2^e in [1/2, 1)
+    // exponent: max * 2^e in [2^(t-1), 2^t), t = 0 (BF16) or 14 (IEEE half)
+    constexpr int t_top = MODE == 4 ? 14 : 0;
+    if (MODE >= 3 && r == 0 && blockIdx.x == 0) {
         double mx = __longlong_as_double((long long)mmax[m]);
         int E = 0;
         if (mx > 0.0) frexp(mx, &E);
-        mbs[m].e = -E;
+        mbs[m].e = t_top - E;
     }
     if (r >= b.R) return;
     const int j = b.j0 + r;
     const double x = mu[j];
     double scale = 1.0;
-    if (MODE == 3) {
+    if (MODE >= 3) {
         double mx = __longlong_as_double((long long)mmax[m]);
         int E = 0;
         if (mx > 0.0) frexp(mx, &E);
-        scale = ldexp(1.0, -E);
+        scale = ldexp(1.0, t_top - E);
     }
     double vmax = 0.0;
     auto put = [&](int n, double v) {
@@ -219,10 +224,20 @@ __global__ void k_legendre_table(int trunc, const double *mu, const double *diag
         } else if (MODE == 2) {
             ((float *)tab_kr)[ikr] = (float)v;
             ((float *)tab_rk)[irk] = (float)v;
-        } else {
+        } else if (MODE == 3) {
             double vs = v * scale;
             unsigned short hi = bf16_rne((float)vs);
             unsigned short lo = bf16_rne((float)(vs - (double)bf16_to_f(hi)));
+            ((unsigned short *)tab_kr)[ikr] = hi;
+            ((unsigned short *)tab_rk)[irk] = hi;
+            ((unsigned short *)lo_kr)[ikr] = lo;
+            ((unsigned short *)lo_rk)[irk] = lo;
+        } else {
+            double vs = v * scale;
+            _Float16 h = (_Float16)(float)vs;
+            _Float16 l = (_Float16)(float)(vs - (double)h);
+            unsigned short hi = __builtin_bit_cast(unsigned short, h);
+            unsigned short lo = __builtin_bit_cast(unsigned short, l);
             ((unsigned short *)tab_kr)[ikr] = hi;
             ((unsigned short *)tab_rk)[irk] = hi;
             ((unsigned short *)lo_kr)[ikr] = lo;
@@ -286,8 +301,12 @@ hipError_t launch_legendre_tables(Plan &p, hipStream_t s)
         k_legendre_table<0><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, nullptr,
                                                   nullptr, nullptr, nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        k_legendre_table<3><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, p.d_tab_kr,
-                                                  p.d_tab_rk, p.d_tab_kr_lo, p.d_tab_rk_lo);
+        if (p.prec == SHTX_FP16X3)
+            k_legendre_table<4><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, p.d_tab_kr,
+                                                      p.d_tab_rk, p.d_tab_kr_lo, p.d_tab_rk_lo);
+        else
+            k_legendre_table<3><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, p.d_tab_kr,
+                                                      p.d_tab_rk, p.d_tab_kr_lo, p.d_tab_rk_lo);
     }
     return hipGetLastError();
 }

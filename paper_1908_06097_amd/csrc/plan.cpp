@@ -159,7 +159,7 @@ void free_plan(Plan &p)
     void *ptrs[] = {p.d_mu, p.d_w, p.d_diag, p.d_tab_kr, p.d_tab_rk, p.d_tab_kr_lo,
                     p.d_tab_rk_lo, p.d_mmax, p.d_mb, p.d_inv_items, p.d_dir_items,
                     p.d_rings, p.d_ring_four_off, p.d_ring_pair, p.d_ring_q, p.d_fft_items, p.d_passes,
-                    p.d_twid, p.d_four};
+                    p.d_twid, p.d_four, p.d_fmax};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &g : p.graphs)
@@ -298,7 +298,7 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
 {
     if (trunc < 0 || nfld < 1 || nlat < 2) return SHTX_EINVAL;
     if (grid != SHTX_GRID_FULL && grid != SHTX_GRID_OCTAHEDRAL) return SHTX_EINVAL;
-    if (prec != SHTX_FP64 && prec != SHTX_FP32 && prec != SHTX_BF16X3) return SHTX_EINVAL;
+    if (prec != SHTX_FP64 && prec != SHTX_FP32 && !split_form(prec)) return SHTX_EINVAL;
     if (nlat % 2) return SHTX_EUNSUPPORTED;
     if (grid == SHTX_GRID_FULL && (nlon_full < 2 || nlon_full % 2)) return nlon_full < 2 ? SHTX_EINVAL : SHTX_EUNSUPPORTED;
     if (trunc > 4095 || nlat > 16384 || nfld > (1 << 20)) return SHTX_EUNSUPPORTED;
@@ -355,7 +355,7 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
     p.legendre_flops = flops;
 
     size_t tab_el = prec == SHTX_FP64 ? 8 : prec == SHTX_FP32 ? 4 : 2;
-    p.table_bytes = (prec == SHTX_BF16X3 ? 4 : 2) * tab_el * p.tab_elems;
+    p.table_bytes = (split_form(prec) ? 4 : 2) * tab_el * p.tab_elems;
 
     // ---- ring FFT plans and twiddle pool --------------------------------------
     const bool dbl = prec == SHTX_FP64;
@@ -525,7 +525,7 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
     PLAN_TRY(hipMalloc(&p.d_tab_kr, tab_el * p.tab_elems));
     PLAN_TRY(hipMalloc(&p.d_tab_rk, tab_el * p.tab_elems));
     p.table_bytes = 2 * tab_el * p.tab_elems;
-    if (prec == SHTX_BF16X3) {
+    if (split_form(prec)) {
         PLAN_TRY(hipMalloc(&p.d_tab_kr_lo, tab_el * p.tab_elems));
         PLAN_TRY(hipMalloc(&p.d_tab_rk_lo, tab_el * p.tab_elems));
         p.table_bytes *= 2;
@@ -546,6 +546,13 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
     std::vector<double> w(nlat);
     PLAN_TRY(hipMemcpy(w.data(), p.d_w, sizeof(double) * nlat, hipMemcpyDeviceToHost));
     for (int j = 0; j < nlat; ++j) p.rings[j].w = w[j];
+    for (int j = 0; j < nlat / 2; ++j) p.qmax = std::max(p.qmax, 0.5 * w[j]);
+    if (prec == SHTX_FP16X3) {
+        // written by every transform before it is read; zero until then (the
+        // autotuner times the GEMMs alone)
+        PLAN_TRY(hipMalloc(&p.d_fmax, sizeof(unsigned) * nfld));
+        PLAN_TRY(hipMemset(p.d_fmax, 0, sizeof(unsigned) * nfld));
+    }
 
     const bool dbl = prec == SHTX_FP64;
     size_t celem = dbl ? 16 : 8;

@@ -108,6 +108,9 @@ struct FftItem {
 
 enum TransformKind { kInverse = 0, kDirect = 1, kInverseAdj = 2, kDirectAdj = 3 };
 
+// The split-precision forms: hi + lo halves of bfloat16 or IEEE half.
+inline bool split_form(int prec) { return prec == SHTX_BF16X3 || prec == SHTX_FP16X3; }
+
 struct Plan {
     int trunc = 0, grid = 0, nlat = 0, nlon_full = 0, nfld = 0, prec = 0;
     unsigned flags = 0;
@@ -157,6 +160,10 @@ struct Plan {
     int64_t twid_elems = 0;  // complex entries in the pool
     std::vector<double> twid_host;  // pool (re, im) before upload
     void *d_four = nullptr;  // Fourier workspace [ring][m][nfld] complex
+    // SHTX_FP16X3: per field, the largest magnitude (float bits) of the data
+    // the next Legendre GEMM splits (spectral input or Fourier workspace)
+    unsigned *d_fmax = nullptr;
+    double qmax = 0.0;  // max over northern rings of w_j / 2
     int64_t tab_elems = 0;   // elements per table layout
     size_t table_bytes = 0, workspace_bytes = 0;
     double legendre_flops = 0.0;
@@ -189,13 +196,18 @@ hipError_t wait_done(Plan &p);
 // Kernel launchers (each checks its launch shape on the host first).
 hipError_t launch_gauss_nodes(int nlat, double *mu, double *w, hipStream_t s);
 hipError_t launch_legendre_tables(Plan &p, hipStream_t s);
-hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, hipStream_t s);
-hipError_t launch_gemm_direct(const Plan &p, const void *four, void *spec, bool adjoint,
+// `fmax` is the per-field maxima buffer of a SHTX_FP16X3 plan (nfld words;
+// ignored by the other forms): the plan's own, or a caller-provided one.
+hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, unsigned *fmax, hipStream_t s);
+hipError_t launch_gemm_direct(const Plan &p, const void *four, void *spec, bool adjoint, unsigned *fmax,
                               hipStream_t s);
 hipError_t launch_fft_c2r(const Plan &p, const void *four, void *grid, bool adjoint,
                           hipStream_t s);
-hipError_t launch_fft_r2c(const Plan &p, const void *grid, void *four, bool adjoint,
+hipError_t launch_fft_r2c(const Plan &p, const void *grid, void *four, bool adjoint, unsigned *fmax,
                           hipStream_t s);
+// Fields per ring-FFT block are at most this many when the r2c kernel also
+// records each field's largest output magnitude (SHTX_FP16X3 plans).
+constexpr int kFmaxFields = 1024;
 
 // Host checks that every kernel's work list and launch shape stay inside the
 // plan's arrays and the kernels' compile-time limits (no device access).

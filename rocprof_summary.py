@@ -29,20 +29,23 @@ COPY_BYTES = 1 << 30
 
 
 def classify(name):
-    if "k_leg_mfma" in name or "k_leg_bf16x3" in name:
+    if "k_spec_absmax" in name:
+        # the split-half form's per-field maxima, launched with the inverse GEMM
+        return "legendre_inverse_gemm"
+    if "k_leg_mfma" in name or "k_leg_split" in name:
         # the inverse-shaped instantiation has template argument INV = true
-        # (5th of k_leg_mfma<T, BM, BN, BK, INV, NW>, 4th of k_leg_bf16x3)
+        # (5th of k_leg_mfma<T, BM, BN, BK, INV, NW> and of
+        # k_leg_split<F16, BM, BN, BK, INV>)
         args = re.search(r"<([^<>]*)>", name)
         if args:
             parts = [x.strip() for x in args.group(1).split(",")]
-            pos = 4 if "k_leg_mfma" in name else 3
-            inv = len(parts) > pos and parts[pos] == "true"
+            inv = len(parts) > 4 and parts[4] == "true"
         else:
-            inv = "Lb1E" in name
+            inv = name.endswith("Lb1EEEvNS0_8GemmArgsE") or "Lb1ELi8E" in name or "Lb1ELi4E" in name
         return "legendre_inverse_gemm" if inv else "legendre_direct_gemm"
     if "k_fft_c2r" in name:
         return "ring_fft_c2r"
-    if "k_fft_r2c" in name:
+    if "k_fft_r2c" in name or "k_zero_u32" in name:
         return "ring_fft_r2c"
     if "copy" in name.lower() or "elementwise" in name.lower():
         return "copy"

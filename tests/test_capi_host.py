@@ -10,7 +10,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 # Largest LDS complex values per FFT block (single-precision FFTs also serve
 # BF16x3) and the autotuner's other two blockings.
-FFT_CAPS = {"fp32": (8192, 4096, 2730), "bf16x3": (8192, 4096, 2730), "fp64": (8192, 4096, 2730)}
+FFT_CAPS = {"fp32": (8192, 4096, 2730), "bf16x3": (8192, 4096, 2730), "fp16x3": (8192, 4096, 2730),
+            "fp64": (8192, 4096, 2730)}
 
 
 def _declared():
@@ -71,7 +72,7 @@ def test_python_binding_refuses_without_gpu():
         shtx.Plan(31, "octahedral", 64, 1, "fp32")
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_plan_check_all_workloads(lib, prec):
     """Host dry run of every workload's plan: geometry and every kernel's
     launch shape pass the library's own bounds checks, without a GPU."""
@@ -98,7 +99,8 @@ def test_plan_check_rejects(lib):
 
 @pytest.mark.parametrize("prec,shapes", [("fp32", [(128, 128), (64, 128), (128, 64)]),
                                          ("fp64", [(64, 64), (32, 64), (64, 32)]),
-                                         ("bf16x3", [(128, 128), (64, 128)])])
+                                         ("bf16x3", [(128, 128), (64, 128)]),
+                                         ("fp16x3", [(128, 128), (64, 128)])])
 def test_plan_check_every_tuning_shape(lib, prec, shapes):
     """Every tile shape and FFT blocking the autotuner may pick passes the
     library's launch-shape checks on the workloads (host dry run)."""

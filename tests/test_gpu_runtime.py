@@ -48,7 +48,7 @@ def test_graph_replay_matches_eager(prec):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_graph_path_matches_oracle(prec):
     """The hipGraph replay path (the one the benchmark times) against the
     oracle on a multi-tile shape, every transform kind, four replays each."""
@@ -98,7 +98,7 @@ def test_power_of_two_scaling_is_exact_and_zero_maps_to_zero():
     assert torch.count_nonzero(plan.dir(torch.zeros_like(g))) == 0
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
 def test_fields_are_independent(prec):
     torch, shtx = _env()
     plan = shtx.Plan(127, "octahedral", 256, 70, prec)

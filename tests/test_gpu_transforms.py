@@ -3,7 +3,8 @@
 Every call goes through the C ABI (via the thin Python binding).  Inputs are
 the seeded synthetic spectra of ``synth_inputs``; expected values come only
 from ``oracle``.  Tolerances: FP64 1e-12 (max relative), FP32 1e-5 (RMS),
-split BF16 1e-4 (RMS), per field, on spectral and grid outputs.
+split BF16 and split IEEE half 1e-4 (RMS), per field, on spectral and grid
+outputs.
 """
 import numpy as np
 import pytest
@@ -13,8 +14,8 @@ from error_metrics import grid_errors, spec_errors
 
 pytestmark = pytest.mark.gpu
 
-TOL_RMS = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4}
-TOL_MAX = {"fp64": 1e-12, "fp32": 1e-4, "bf16x3": 1e-3}
+TOL_RMS = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4, "fp16x3": 1e-4}
+TOL_MAX = {"fp64": 1e-12, "fp32": 1e-4, "bf16x3": 1e-3, "fp16x3": 1e-3}
 
 
 def _torch():
@@ -62,7 +63,7 @@ def test_nodes_bitwise(nlat):
     assert np.all(np.abs(w - w_o) <= np.spacing(w_o)), np.max(np.abs(w - w_o) / np.spacing(w_o))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-7), ("bf16x3", 1.5e-5)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 2e-7), ("bf16x3", 1.5e-5), ("fp16x3", 1e-6)])
 def test_legendre_tables(prec, tol):
     shtx, o = _shtx(), _oracle()
     N, nlat = 255, 512
@@ -116,7 +117,7 @@ def _check_all(plan, N, nlon, key, fields, prec):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 @pytest.mark.parametrize("shape", ["T31_O32_F3", "T63_full_F2", "T159_O160_F70"])
 def test_transform_parity(prec, shape):
     shtx, o = _shtx(), _oracle()
@@ -292,6 +293,14 @@ def test_tco1279_o1280_bf16x3_411_fields():
 
 def test_tco1279_o1280_bf16x3_adjoints():
     _full_size("tco1279_o1280", "bf16x3", SAMPLE_16, adjoints=True, forward=False)
+
+
+def test_tco639_o640_fp16x3_411_fields():
+    _full_size("tco639_o640", "fp16x3", SAMPLE_32)
+
+
+def test_tco1279_o1280_fp16x3_411_fields():
+    _full_size("tco1279_o1280", "fp16x3", SAMPLE_16, adjoints=True)
 
 
 def test_tco1279_o1280_fp64_411_fields():

@@ -13,10 +13,11 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = {"fp32": [(128, 128), (64, 128), (128, 64)],
           "fp64": [(64, 64), (32, 64), (64, 32)],
-          "bf16x3": [(128, 128), (64, 128)]}
+          "bf16x3": [(128, 128), (64, 128)],
+          "fp16x3": [(128, 128), (64, 128)]}
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16x3", "fp16x3"])
 def test_every_tile_shape_matches_oracle(prec):
     shtx = _shtx()
     N, nlat, F = 159, 320, 70
