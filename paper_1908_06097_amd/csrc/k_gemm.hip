@@ -22,6 +22,7 @@
 // is this library's own.
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include "shtx_internal.h"
 
@@ -670,57 +671,66 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
     const bool mfma_on = __builtin_amdgcn_readfirstlane(
         (row0 + wr < (INVERSE ? b.R : b.K0) && col0 + wc < ncol) ? 1 : 0);
 
-    if (!INVERSE) meta(0, mp1, mq1);
-    load(0);
-    if (!INVERSE && nstages > 1) meta(BK, mp2, mq2);
-    for (int s = 0; s < nstages; ++s) {
-        store();  // uses the weights mq1 of stage s
-        if (!INVERSE && s + 1 < nstages) {
+    // The K loop, in two copies: with MFMAs, and without them for a wave
+    // whose sub-tile is wholly ragged (a wave-uniform branch outside the
+    // loop keeps the accumulators in the MFMA accumulation registers).
+    auto kloop = [&](auto with_mfma) __attribute__((always_inline)) {
+        if (!INVERSE) meta(0, mp1, mq1);
+        load(0);
+        if (!INVERSE && nstages > 1) meta(BK, mp2, mq2);
+        for (int s = 0; s < nstages; ++s) {
+            store();  // uses the weights mq1 of stage s
+            if (!INVERSE && s + 1 < nstages) {
 #pragma unroll
-            for (int u = 0; u < NMU; ++u)
+                for (int u = 0; u < NMU; ++u)
 #pragma unroll
-                for (int q = 0; q < NMQ; ++q) {
-                    mp1[u][q] = mp2[u][q];
-                    mq1[u][q] = mq2[u][q];
-                }
-        }
-        __syncthreads();
-        if (s + 1 < nstages) load((s + 1) * BK);  // in flight during the MFMAs
-        if (!INVERSE && s + 2 < nstages) meta((s + 2) * BK, mp2, mq2);
-        if (mfma_on) {
-#pragma unroll
-            for (int q = 0; q < BK; q += 32) {
-                const int kq = q + 8 * (lane >> 4);
-#pragma unroll
-                for (int p = 0; p < 2; ++p) {
-                    u32x4 ah[FM], al[FM], bh[FN], bl[FN];
-#pragma unroll
-                    for (int i = 0; i < FM; ++i) {
-                        const int ai = wr + i * 16 + (lane & 15);
-                        ah[i] = *reinterpret_cast<const u32x4 *>(&As[p][0][ai][kq]);
-                        al[i] = *reinterpret_cast<const u32x4 *>(&As[p][1][ai][kq]);
+                    for (int q = 0; q < NMQ; ++q) {
+                        mp1[u][q] = mp2[u][q];
+                        mq1[u][q] = mq2[u][q];
                     }
+            }
+            __syncthreads();
+            if (s + 1 < nstages) load((s + 1) * BK);  // in flight during the MFMAs
+            if (!INVERSE && s + 2 < nstages) meta((s + 2) * BK, mp2, mq2);
+            if constexpr (decltype(with_mfma)::value) {
 #pragma unroll
-                    for (int j = 0; j < FN; ++j) {
-                        const int bj = wc + j * 16 + (lane & 15);
-                        bh[j] = *reinterpret_cast<const u32x4 *>(&Bs[p][0][bj][kq]);
-                        bl[j] = *reinterpret_cast<const u32x4 *>(&Bs[p][1][bj][kq]);
-                    }
+                for (int q = 0; q < BK; q += 32) {
+                    const int kq = q + 8 * (lane >> 4);
 #pragma unroll
-                    for (int i = 0; i < FM; ++i)
+                    for (int p = 0; p < 2; ++p) {
+                        u32x4 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+                        for (int i = 0; i < FM; ++i) {
+                            const int ai = wr + i * 16 + (lane & 15);
+                            ah[i] = *reinterpret_cast<const u32x4 *>(&As[p][0][ai][kq]);
+                            al[i] = *reinterpret_cast<const u32x4 *>(&As[p][1][ai][kq]);
+                        }
 #pragma unroll
                         for (int j = 0; j < FN; ++j) {
-                            f32x4 c = acc[p][i][j];
-                            c = mfma_split<F16>(ah[i], bl[j], c);
-                            c = mfma_split<F16>(al[i], bh[j], c);
-                            c = mfma_split<F16>(ah[i], bh[j], c);
-                            acc[p][i][j] = c;
+                            const int bj = wc + j * 16 + (lane & 15);
+                            bh[j] = *reinterpret_cast<const u32x4 *>(&Bs[p][0][bj][kq]);
+                            bl[j] = *reinterpret_cast<const u32x4 *>(&Bs[p][1][bj][kq]);
                         }
+#pragma unroll
+                        for (int i = 0; i < FM; ++i)
+#pragma unroll
+                            for (int j = 0; j < FN; ++j) {
+                                f32x4 c = acc[p][i][j];
+                                c = mfma_split<F16>(ah[i], bl[j], c);
+                                c = mfma_split<F16>(al[i], bh[j], c);
+                                c = mfma_split<F16>(ah[i], bh[j], c);
+                                acc[p][i][j] = c;
+                            }
+                    }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
-    }
+    };
+    if (mfma_on)
+        kloop(std::true_type{});
+    else
+        kloop(std::false_type{});
 
     // unscaling exponent of each of the lane's columns: e_m (+ E_f)
     int eu[FN];
