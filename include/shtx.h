@@ -76,7 +76,8 @@ enum shtx_status {
     SHTX_EINVAL = -1,      /* bad argument, null or overlapping pointers */
     SHTX_ENOMEM = -2,      /* device or host allocation failed at plan time */
     SHTX_EHIP = -3,        /* a HIP runtime call or kernel launch failed */
-    SHTX_EUNSUPPORTED = -4 /* valid but unsupported (odd nlat, odd ring length) */
+    SHTX_EUNSUPPORTED = -4, /* valid but unsupported (odd nlat, odd ring length) */
+    SHTX_ESCRATCH = -5      /* needs more scratch than shtx_inv_trans_noalloc's static array */
 };
 
 /* Flags for shtx_plan_create. */
@@ -163,6 +164,25 @@ int shtx_dir_trans(shtx_plan p, const void *grid_d, void *spec_d, void *hip_stre
 int shtx_inv_trans_adj(shtx_plan p, const void *grid_d, void *spec_d, void *hip_stream);
 /* Adjoint of the direct transform: spec -> grid. */
 int shtx_dir_trans_adj(shtx_plan p, const void *spec_d, void *grid_d, void *hip_stream);
+
+/* For callers that cannot allocate device memory at transform time (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): shtx_inv_trans with the transform's scratch -- the Fourier
+ * workspace [ring][m][nfld] and, for SHTX_FP16X3 plans, the per-field maxima
+ * -- in a static device array of SHTX_NOALLOC_SCRATCH_BYTES bytes that the
+ * library holds on each GPU it runs on until the process ends, instead of
+ * the plan's workspace.  Same arguments, layouts, checks and result as
+ * shtx_inv_trans (the same kernels; the output is bit-identical); it calls no
+ * allocator.  A plan whose workspace needs more than the array holds
+ * (nfour * nfld complex values, plus nfld words rounded to 256 bytes for
+ * SHTX_FP16X3) gets SHTX_ESCRATCH and nothing is launched.  The array is
+ * located once per device, when a plan is created with that device current;
+ * the call must be made with the plan's device current (else SHTX_EINVAL).
+ * Every call on one GPU shares that GPU's array, from any plan: calls that
+ * overlap in time on one GPU (other streams, other threads) race and give
+ * undefined results.  Runs eagerly (no graph replay, no kernel timing). */
+#define SHTX_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int shtx_inv_trans_noalloc(shtx_plan p, const void *spec_d, void *grid_d, void *hip_stream);
 
 /* Kernel timing.  With SHTX_FLAG_TIMING at plan creation every transform
  * call records HIP events around each of its kernels on the call's stream

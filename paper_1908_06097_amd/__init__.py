@@ -30,7 +30,7 @@ _lib = None
 
 _EXPORTS = ("shtx_plan_create", "shtx_plan_check", "shtx_plan_check_shapes", "shtx_plan_set_shapes", "shtx_plan_info", "shtx_plan_ring_lengths", "shtx_plan_nodes",
             "shtx_plan_legendre", "shtx_inv_trans", "shtx_dir_trans", "shtx_inv_trans_adj",
-            "shtx_dir_trans_adj", "shtx_timing_reset", "shtx_timing_enable", "shtx_timing_read", "shtx_plan_destroy",
+            "shtx_dir_trans_adj", "shtx_inv_trans_noalloc", "shtx_timing_reset", "shtx_timing_enable", "shtx_timing_read", "shtx_plan_destroy",
             "shtx_strerror")
 
 
@@ -65,7 +65,8 @@ def load_library():
     lib.shtx_plan_ring_lengths.argtypes = [vp, ctypes.c_void_p]
     lib.shtx_plan_nodes.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
     lib.shtx_plan_legendre.argtypes = [vp, i32, ctypes.c_void_p]
-    for name in ("shtx_inv_trans", "shtx_dir_trans", "shtx_inv_trans_adj", "shtx_dir_trans_adj"):
+    for name in ("shtx_inv_trans", "shtx_dir_trans", "shtx_inv_trans_adj", "shtx_dir_trans_adj",
+                 "shtx_inv_trans_noalloc"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp]
     lib.shtx_timing_reset.argtypes = [vp]
     lib.shtx_timing_enable.argtypes = [vp, i32]
@@ -201,6 +202,12 @@ class Plan:
     def inv(self, spec, out=None):
         """Inverse transform: spectral [nfld, nspec] -> grid [nfld, npts]."""
         return self._run("shtx_inv_trans", spec, "spec", "grid", out)
+
+    def inv_noalloc(self, spec, out):
+        """Inverse transform through shtx_inv_trans_noalloc: the library's static
+        scratch instead of the plan's workspace (`out` is required, so that
+        the call allocates nothing)."""
+        return self._run("shtx_inv_trans_noalloc", spec, "spec", "grid", out)
 
     def dir(self, grid, out=None):  # noqa: A003 - the transform's name
         """Direct transform: grid [nfld, npts] -> spectral [nfld, nspec]."""

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "shtx_internal.h"
@@ -177,6 +178,40 @@ int run(shtx_plan h, int kind, const void *in, void *out, void *stream)
     return hip_status(e);
 }
 
+// ---------------------------------------------------------------------------
+// Static scratch of shtx_inv_trans_noalloc.  In host code `scratch` names a
+// host-side stand-in, not device memory: kernels and copies get the address
+// hipGetSymbolAddress returns for the device, found once per device.
+// ---------------------------------------------------------------------------
+__device__ __attribute__((aligned(256))) unsigned char scratch[SHTX_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_dev[kMaxDevices];   // device address of `scratch` per device (null: not found)
+bool scratch_tried[kMaxDevices];
+
+// Find `scratch` on `device`, which must be the current device (plan creation).
+void locate_scratch(int device)
+{
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (device < 0 || device >= kMaxDevices || scratch_tried[device]) return;
+    scratch_tried[device] = true;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && ptr) {
+        scratch_dev[device] = ptr;
+    } else {
+        (void)hipGetLastError();
+        if (std::getenv("SHTX_DEBUG")) std::fprintf(stderr, "shtx: static scratch not found: %d\n", (int)e);
+    }
+}
+
+void *scratch_on(int device)
+{
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    return device >= 0 && device < kMaxDevices ? scratch_dev[device] : nullptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -195,6 +230,7 @@ int shtx_plan_create(shtx_plan *out, int trunc, int grid, int nlat, int nlon_ful
         delete h;
         return rc;
     }
+    locate_scratch(h->p.device);  // the plan's device is current here
     *out = h;
     return SHTX_OK;
 }
@@ -323,6 +359,31 @@ int shtx_inv_trans(shtx_plan h, const void *spec, void *grid, void *stream)
     return run(h, shtx::kInverse, spec, grid, stream);
 }
 
+int shtx_inv_trans_noalloc(shtx_plan h, const void *spec, void *grid, void *stream)
+{
+    if (!h) return SHTX_EINVAL;
+    Plan &p = h->p;
+    int rc = check_args(p, shtx::kInverse, spec, grid);
+    if (rc != SHTX_OK) return rc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p.device) return SHTX_EINVAL;
+    const size_t celem = p.prec == SHTX_FP64 ? 16 : 8;
+    const size_t four_bytes = (size_t)p.nfour * p.nfld * celem;
+    const size_t fmax_off = (four_bytes + 255) / 256 * 256;
+    const size_t need = p.prec == SHTX_FP16X3 ? fmax_off + sizeof(unsigned) * p.nfld : four_bytes;
+    if (need > SHTX_NOALLOC_SCRATCH_BYTES) return SHTX_ESCRATCH;
+    unsigned char *base = static_cast<unsigned char *>(scratch_on(p.device));
+    if (!base) return SHTX_EHIP;
+    unsigned *fmax = p.prec == SHTX_FP16X3 ? reinterpret_cast<unsigned *>(base + fmax_off) : nullptr;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // the kernels overwrite every workspace entry the FFT reads, and the
+    // maxima are rewritten before use: nothing needs clearing
+    hipError_t e = shtx::launch_gemm_inverse(p, spec, base, fmax, s);
+    if (e == hipSuccess) e = shtx::launch_fft_c2r(p, base, grid, false, s);
+    if (e == hipSuccess) e = mark_done(p, s);
+    return hip_status(e);
+}
+
 int shtx_dir_trans(shtx_plan h, const void *grid, void *spec, void *stream)
 {
     return run(h, shtx::kDirect, grid, spec, stream);
@@ -406,6 +467,7 @@ const char *shtx_strerror(int code)
     case SHTX_ENOMEM: return "out of memory";
     case SHTX_EHIP: return "HIP runtime error";
     case SHTX_EUNSUPPORTED: return "unsupported configuration";
+    case SHTX_ESCRATCH: return "transform needs more scratch than the static array of shtx_inv_trans_noalloc holds";
     default: return "unknown error";
     }
 }
