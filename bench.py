@@ -50,12 +50,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="tco1279_o1280")
     ap.add_argument("--prec", default="fp32", choices=sorted(PEAK_TF))
-    ap.add_argument("--forms", default="fp64,bf16x3",
+    ap.add_argument("--forms", default="fp64,bf16x3,fp16x3",
                     help="extra precision forms timed beside the headline (comma list, or none)")
     ap.add_argument("--form-steps", type=int, default=5)
     ap.add_argument("--kernel-steps", type=int, default=5,
                     help="eager steps with per-kernel events (the roofline figures)")
     ap.add_argument("--no-pair", action="store_true", help="skip the inverse + adjoint-of-inverse pair")
+    ap.add_argument("--no-energy", action="store_true", help="skip the amd-smi energy window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single-core", action="store_true",
                     help="skip the one-thread oracle run of one field")
@@ -122,7 +123,39 @@ def graph_steps(torch, stream, steps, warmup, fn):
     return [a.elapsed_time(b) for a, b in ev], wall
 
 
-def run_form(torch, shtx, wl, prec, steps, warmup, kernel_steps, spec_host, autotune, pair):
+def energy_window(torch, stream, step, step_ms, busy_s=4.0, idle_s=2.5):
+    """Mean GPU power over repeated steps (graph replay) lasting about
+    `busy_s` seconds and over `idle_s` idle seconds just before, through
+    amd-smi; energy per step = mean busy power x median step time."""
+    from energy_meter import EnergyMeter
+    meter = EnergyMeter()
+    if not meter.available:
+        return {"error": meter.error}
+    stream.synchronize()
+    meter.start()
+    time.sleep(idle_s)
+    idle = meter.stop()
+    n = max(10, int(busy_s / max(step_ms * 1e-3, 1e-6)) + 1)
+    meter.start()
+    for _ in range(n):
+        step()
+    stream.synchronize()
+    busy = meter.stop()
+    if busy is None or idle is None:
+        return {"error": meter.error}
+    w = busy["counter_mean_W"]
+    return {"steps": n, "wall_s": busy["wall_s"], "mean_W": w,
+            "J_per_step": w * step_ms * 1e-3 if w else None,
+            "counter_updates": busy["counter_updates"], "counter_span_s": busy["counter_span_s"],
+            "sampled_mean_W": busy["sampled_mean_W"],
+            "sampled_J_per_step": busy["sampled_mean_W"] * step_ms * 1e-3 if busy["sampled_mean_W"] else None,
+            "samples": busy["samples"], "idle_W": idle["counter_mean_W"], "idle_sampled_W": idle["sampled_mean_W"],
+            "method": "amd-smi energy accumulator: energy between its updates inside the window over their "
+                      "timestamps (about one update per second); socket power polled every 10 ms and "
+                      "integrated by the trapezoid rule beside it; J per step = mean power x median step time"}
+
+
+def run_form(torch, shtx, wl, prec, steps, warmup, kernel_steps, spec_host, autotune, pair, energy=False):
     stream = torch.cuda.Stream()  # graph replay needs a non-default stream
     with torch.cuda.stream(stream):
         plan = shtx.Plan(wl.trunc, wl.grid, wl.nlat, wl.nfld, prec, nlon_full=wl.nlon_full, graph=True,
@@ -154,6 +187,8 @@ def run_form(torch, shtx, wl, prec, steps, warmup, kernel_steps, spec_host, auto
                            "fields_per_s": wl.nfld / (statistics.median(pms) * 1e-3),
                            "wall_fields_per_s": wl.nfld * steps / pwall}
             res["adj_out"] = adj
+        if energy:
+            res["energy"] = energy_window(torch, stream, step, res["ms_median"])
         # 2. kernel breakdown: eager launches with per-kernel events
         plan.timing_enable(True)
         step()
@@ -333,7 +368,7 @@ def main():
 
     say(f"headline form {args.prec}")
     res = run_form(torch, shtx, wl, args.prec, args.steps, args.warmup, args.kernel_steps, spec_host,
-                   not args.no_autotune, pair)
+                   not args.no_autotune, pair, energy=not args.no_energy)
     say(f"  {res['fields_per_s']:.1f} fields/s (median {res['ms_median']:.3f} ms, min {res['ms_min']:.3f} ms)")
     roof = roofline_for(res, args.prec)
     dom = max(roof, key=lambda k: roof[k]["ms"])
@@ -369,6 +404,12 @@ def main():
     }
     if pair:
         line["pair_fwd_adj"] = dict(res["pair"], what="inv_trans then inv_trans_adj of its grids (graph replay)")
+    if "energy" in res:
+        en = dict(res["energy"])
+        if en.get("J_per_step"):
+            en["J_per_field_pair"] = en["J_per_step"] / wl.nfld
+            en["fields_per_J"] = wl.nfld / en["J_per_step"]
+        line["energy"] = en
     if not args.no_cpu_baseline:
         say(f"cpu baseline: oracle on {args.cpu_fields or 'about 15 s of'} field(s)")
         cb, g_ref, b_ref, n_ref, cores = cpu_baseline(wl, args.cpu_fields, spec_np, not args.no_single_core)

@@ -3,10 +3,12 @@
 // (its truncation, grid, field count and precision) and keeps the fastest.
 // Results can be kept in a JSON-lines cache named by SHTX_TUNE_CACHE, keyed by
 // device architecture, plan shape and a hash of the kernel sources.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "shtx_internal.h"
 
@@ -72,18 +74,51 @@ void cache_store(const char *path, const std::string &key, const TuneResult &r)
     std::fclose(f);
 }
 
-// Mean milliseconds of `reps` runs of `fn` after one untimed run.
+// Median milliseconds of `reps` separately timed runs of `fn` after one
+// untimed run.
 template <class Fn>
 double time_ms(hipStream_t s, hipEvent_t a, hipEvent_t b, int reps, Fn fn)
 {
     if (fn() != hipSuccess) return -1.0;
-    if (hipEventRecord(a, s) != hipSuccess) return -1.0;
-    for (int i = 0; i < reps; ++i)
-        if (fn() != hipSuccess) return -1.0;
-    if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess) return -1.0;
-    float ms = 0.f;
-    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.0;
-    return ms / reps;
+    std::vector<double> t;
+    for (int i = 0; i < reps; ++i) {
+        if (hipEventRecord(a, s) != hipSuccess || fn() != hipSuccess || hipEventRecord(b, s) != hipSuccess ||
+            hipEventSynchronize(b) != hipSuccess)
+            return -1.0;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return -1.0;
+        t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+// Pseudo-random operands in [-1/2, 1/2) (a 32-bit integer hash of the
+// index), so that the timed kernels see data like the transforms' own:
+// constant or zero operands change the matrix cores' power draw and with it
+// the clock, and timed the shapes in a different order than real data.
+template <typename T>
+__global__ void k_fill_noise(T *x, size_t n, unsigned seed)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        unsigned h = (unsigned)i * 0x9E3779B9u ^ seed;
+        h ^= h >> 16;
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 13;
+        h *= 0xC2B2AE35u;
+        h ^= h >> 16;
+        x[i] = (T)((double)(h >> 8) * (1.0 / 16777216.0) - 0.5);
+    }
+}
+
+hipError_t fill_noise(void *x, size_t bytes, bool dbl, unsigned seed, hipStream_t s)
+{
+    const size_t n = bytes / (dbl ? 8 : 4);
+    if (dbl)
+        k_fill_noise<double><<<1024, 256, 0, s>>>((double *)x, n, seed);
+    else
+        k_fill_noise<float><<<1024, 256, 0, s>>>((float *)x, n, seed);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -104,7 +139,7 @@ int autotune_plan(Plan &p, hipStream_t s)
         void *spec = nullptr, *grid = nullptr;
         hipEvent_t ea = nullptr, eb = nullptr;
         int rc = SHTX_OK;
-        const int reps = 3;
+        const int reps = 5;
         auto fail = [&](int code) {
             rc = code;
             return code;
@@ -113,18 +148,19 @@ int autotune_plan(Plan &p, hipStream_t s)
             hipMalloc(&grid, rbytes * p.nfld * p.npts) != hipSuccess || hipEventCreate(&ea) != hipSuccess ||
             hipEventCreate(&eb) != hipSuccess)
             fail(SHTX_ENOMEM);
-        // nonzero finite operands (every byte 0x3C: 0.0115 in single, 1.5e-18
-        // in double precision), so that the timed kernels do real arithmetic
-        if (rc == SHTX_OK && (hipMemsetAsync(spec, 0x3C, cbytes * p.nfld * p.nspec, s) != hipSuccess ||
-                              hipMemsetAsync(grid, 0x3C, rbytes * p.nfld * p.npts, s) != hipSuccess ||
-                              hipMemsetAsync(p.d_four, 0x3C, cbytes * p.nfld * p.nfour, s) != hipSuccess))
+        if (rc == SHTX_OK && (fill_noise(spec, cbytes * p.nfld * p.nspec, dbl, 1u, s) != hipSuccess ||
+                              fill_noise(grid, rbytes * p.nfld * p.npts, dbl, 2u, s) != hipSuccess ||
+                              fill_noise(p.d_four, cbytes * p.nfld * p.nfour, dbl, 3u, s) != hipSuccess))
             fail(SHTX_EHIP);
 
         int cbm[8], cbn[8];
         const int nc = gemm_tile_candidates(p.prec, cbm, cbn, 8);
         double bi = 1e300, bd = 1e300;
-        // inverse-shaped and direct-shaped launches are tuned independently
-        for (int c = 0; c < nc && rc == SHTX_OK; ++c) {
+        // inverse-shaped and direct-shaped launches are tuned independently;
+        // the candidates are timed twice, in forward then reverse order, and
+        // each keeps its faster median (clock drift favours neither end)
+        for (int cc = 0; cc < 2 * nc && rc == SHTX_OK; ++cc) {
+            const int c = cc < nc ? cc : 2 * nc - 1 - cc;
             int arc = apply_shapes(p, cbm[c], cbn[c], cbm[c], cbn[c], p.fft_cap);
             if (arc == SHTX_EINVAL || arc == SHTX_EUNSUPPORTED) continue;
             if (arc != SHTX_OK) {
