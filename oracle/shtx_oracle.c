@@ -162,19 +162,44 @@ void oracle_gauss(int nlat, double *mu, double *w)
  *   P̄_{m+1}^m = sqrt(2m+3) mu P̄_m^m,
  *   P̄_n^m = a_nm mu P̄_{n-1}^m - b_nm P̄_{n-2}^m,
  *   a_nm = sqrt((4n^2 - 1) / (n^2 - m^2)),
- *   b_nm = sqrt((2n+1)(n-1-m)(n-1+m) / ((2n-3)(n^2 - m^2))). */
+ *   b_nm = sqrt((2n+1)(n-1-m)(n-1+m) / ((2n-3)(n^2 - m^2))).
+ *
+ * Extended exponent.  Near the poles the sectoral value P̄_m^m ~ s^m leaves
+ * the double range for large m (m log10(1/s) > 300) while the recurrence in
+ * n can bring P̄_n^m back to order one before n reaches the truncation (at
+ * N = 1999 values up to about 5 would be lost, at N = 1279 at most 1e-62).
+ * The column is therefore carried as q 2^E: the sectoral product is
+ * renormalised by frexp after every factor, the recurrence runs on the
+ * scaled values q (scaling by a power of two commutes with rounding, so
+ * nothing changes where the plain recurrence stays in range), q is rescaled
+ * by 2^-600 whenever it exceeds 2^600, and each output is ldexp(q, E): zero
+ * or subnormal while 2^E is that small. */
 static void legendre_column(int trunc, int m, double mu, double s, double *out)
 {
-    double pmm = 1.0;
-    for (int k = 1; k <= m; ++k) pmm *= sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
-    out[0] = pmm;
+    double q = 1.0;
+    int E = 0;
+    for (int k = 1; k <= m; ++k) {
+        int e;
+        q = frexp(q * (sqrt((2.0 * k + 1.0) / (2.0 * k)) * s), &e);
+        E += e;
+    }
+    out[0] = ldexp(q, E);
     if (m == trunc) return;
-    out[1] = sqrt(2.0 * m + 3.0) * mu * pmm;
+    double q0 = q, q1 = sqrt(2.0 * m + 3.0) * mu * q;
+    out[1] = ldexp(q1, E);
     for (int n = m + 2; n <= trunc; ++n) {
         double nn = (double)n * n, mm = (double)m * m;
         double a = sqrt((4.0 * nn - 1.0) / (nn - mm));
         double b = sqrt((2.0 * n + 1.0) * (n - 1.0 - m) * (n - 1.0 + m) / ((2.0 * n - 3.0) * (nn - mm)));
-        out[n - m] = a * mu * out[n - m - 1] - b * out[n - m - 2];
+        double q2 = a * mu * q1 - b * q0;
+        if (fabs(q2) > 0x1p600) {
+            q1 *= 0x1p-600;
+            q2 *= 0x1p-600;
+            E += 600;
+        }
+        out[n - m] = ldexp(q2, E);
+        q0 = q1;
+        q1 = q2;
     }
 }
 

@@ -203,6 +203,35 @@ def test_legendre_addition_theorem_high_degree():
         assert np.max(np.abs(tot / (2 * n + 1) - 1)) < 1e-10, x
 
 
+def test_legendre_addition_theorem_beyond_double_range():
+    """The addition theorem at every n <= 1999 (TCo1999) at points where, for
+    some m, the sectoral value P̄_m^m lies far below the double range while
+    P̄_n^m at higher n is of order one: a seed that underflows to zero would
+    drop those terms (squares up to about 25) from the sum."""
+    o = _orc()
+    N = 1999
+    mu2000, _ = o.gauss(4000)
+    # 0.95, 0.9 and node 600 of O2000 (mu = 0.8908) lose terms up to 5.0,
+    # 4.6 and 3.2 with an underflowing seed
+    for x in (0.95, 0.9, float(mu2000[600])):
+        s = np.sqrt((1 - x) * (1 + x))
+        # log10 of P̄_m^m = prod_k sqrt((2k+1)/(2k)) s, in closed form
+        k = np.arange(1, N + 1)
+        log_pmm = np.concatenate([[0.0], np.cumsum(0.5 * np.log10((2 * k + 1) / (2 * k)) + np.log10(s))])
+        tot = o.legendre(N, 0, [x])[0] ** 2
+        lost = 0.0
+        for m in range(1, N + 1):
+            col = o.legendre(N, m, [x])[0]
+            tot[m:] += 2 * col ** 2
+            if log_pmm[m] < -310:
+                lost = max(lost, float(np.max(np.abs(col))))
+        n = np.arange(N + 1)
+        assert np.max(np.abs(tot / (2 * n + 1) - 1)) < 1e-10, x
+        # the point exercises the extended range: columns whose seed is below
+        # 1e-310 still reach values above 1
+        assert lost > 1.0, (x, lost)
+
+
 # --------------------------------------------------------------------------
 # Ring DFTs
 # --------------------------------------------------------------------------
