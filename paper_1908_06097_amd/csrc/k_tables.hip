@@ -150,19 +150,28 @@ __global__ void k_gauss_nodes(int nlat, double *mu, double *w)
 #pragma clang fp contract(fast)
 
 // Sectoral seeds P̄_m^m(mu_j) = prod_{k<=m} sqrt((2k+1)/(2k)) s_j, one thread per
-// northern ring, s_j = sqrt((1 - mu_j)(1 + mu_j)).
-__global__ void k_sectoral(int nl, int trunc, const double *mu, double *diag)
+// northern ring, s_j = sqrt((1 - mu_j)(1 + mu_j)), kept as q 2^E with q in
+// [1/2, 1) (frexp after every factor): near the poles the product leaves the
+// double range for large m (m log10(1/s) > 300) while the recurrence in n can
+// bring P̄_n^m back to order one before n reaches the truncation (TCo1999).
+__global__ void k_sectoral(int nl, int trunc, const double *mu, double *diag, int *diag_e)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= nl) return;
     double x = mu[j];
     double s = sqrt((1.0 - x) * (1.0 + x));
-    double pmm = 1.0;
+    double q = 1.0;
+    int E = 0;
     double *d = diag + (int64_t)j * (trunc + 1);
+    int *de = diag_e + (int64_t)j * (trunc + 1);
     d[0] = 1.0;
+    de[0] = 0;
     for (int k = 1; k <= trunc; ++k) {
-        pmm *= sqrt((2.0 * k + 1.0) / (2.0 * k)) * s;
-        d[k] = pmm;
+        int e;
+        q = frexp(q * (sqrt((2.0 * k + 1.0) / (2.0 * k)) * s), &e);
+        E += e;
+        d[k] = q;
+        de[k] = E;
     }
 }
 
@@ -184,7 +193,7 @@ __device__ inline float bf16_to_f(unsigned short h) { return __uint_as_float((un
 // to that largest entry of at most 2^-38).  Both table layouts are written:
 // kr = [p][k][r] and rk = [p][r][k] (k = (n - m - p) / 2).
 template <int MODE>
-__global__ void k_legendre_table(int trunc, const double *mu, const double *diag, MBlock *mbs,
+__global__ void k_legendre_table(int trunc, const double *mu, const double *diag, const int *diag_e, MBlock *mbs,
                                  unsigned long long *mmax, void *tab_kr, void *tab_rk,
                                  void *lo_kr, void *lo_rk)
 {
@@ -244,17 +253,26 @@ __global__ void k_legendre_table(int trunc, const double *mu, const double *diag
             ((unsigned short *)lo_rk)[irk] = lo;
         }
     };
+    // the column runs on values scaled by 2^-E (E <= 0 from the seed; a power
+    // of two commutes with rounding), rescaled by 2^-600 whenever it exceeds
+    // 2^600; each stored value is ldexp(p, E)
     double p0 = diag[(int64_t)j * (trunc + 1) + m];
-    put(m, p0);
+    int E = diag_e[(int64_t)j * (trunc + 1) + m];
+    put(m, ldexp(p0, E));
     if (m < trunc) {
         double p1 = sqrt(2.0 * m + 3.0) * x * p0;
-        put(m + 1, p1);
+        put(m + 1, ldexp(p1, E));
         for (int n = m + 2; n <= trunc; ++n) {
             double nn = (double)n * n, mm = (double)m * m;
             double a = sqrt((4.0 * nn - 1.0) / (nn - mm));
             double bb = sqrt((2.0 * n + 1.0) * (n - 1.0 - m) * (n - 1.0 + m) / ((2.0 * n - 3.0) * (nn - mm)));
             double p2 = a * x * p1 - bb * p0;
-            put(n, p2);
+            if (fabs(p2) > 0x1p600) {
+                p1 *= 0x1p-600;
+                p2 *= 0x1p-600;
+                E += 600;
+            }
+            put(n, ldexp(p2, E));
             p0 = p1;
             p1 = p2;
         }
@@ -288,24 +306,24 @@ hipError_t launch_legendre_tables(Plan &p, hipStream_t s)
     if (e == hipSuccess && p.d_tab_rk_lo) e = hipMemsetAsync(p.d_tab_rk_lo, 0, el * p.tab_elems, s);
     if (e == hipSuccess) e = hipMemsetAsync(p.d_mmax, 0, sizeof(unsigned long long) * (N + 1), s);
     if (e != hipSuccess) return e;
-    k_sectoral<<<(NL + 127) / 128, 128, 0, s>>>(NL, N, p.d_mu, p.d_diag);
+    k_sectoral<<<(NL + 127) / 128, 128, 0, s>>>(NL, N, p.d_mu, p.d_diag, p.d_diag_e);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     dim3 grid((NL + 127) / 128, N + 1);
     if (p.prec == SHTX_FP64) {
-        k_legendre_table<1><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, p.d_tab_kr,
+        k_legendre_table<1><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_diag_e, p.d_mb, p.d_mmax, p.d_tab_kr,
                                                   p.d_tab_rk, nullptr, nullptr);
     } else if (p.prec == SHTX_FP32) {
-        k_legendre_table<2><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, p.d_tab_kr,
+        k_legendre_table<2><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_diag_e, p.d_mb, p.d_mmax, p.d_tab_kr,
                                                   p.d_tab_rk, nullptr, nullptr);
     } else {
-        k_legendre_table<0><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, nullptr,
+        k_legendre_table<0><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_diag_e, p.d_mb, p.d_mmax, nullptr,
                                                   nullptr, nullptr, nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (p.prec == SHTX_FP16X3)
-            k_legendre_table<4><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, p.d_tab_kr,
+            k_legendre_table<4><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_diag_e, p.d_mb, p.d_mmax, p.d_tab_kr,
                                                       p.d_tab_rk, p.d_tab_kr_lo, p.d_tab_rk_lo);
         else
-            k_legendre_table<3><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_mb, p.d_mmax, p.d_tab_kr,
+            k_legendre_table<3><<<grid, 128, 0, s>>>(N, p.d_mu, p.d_diag, p.d_diag_e, p.d_mb, p.d_mmax, p.d_tab_kr,
                                                       p.d_tab_rk, p.d_tab_kr_lo, p.d_tab_rk_lo);
     }
     return hipGetLastError();

@@ -159,7 +159,7 @@ void free_plan(Plan &p)
     void *ptrs[] = {p.d_mu, p.d_w, p.d_diag, p.d_tab_kr, p.d_tab_rk, p.d_tab_kr_lo,
                     p.d_tab_rk_lo, p.d_mmax, p.d_mb, p.d_inv_items, p.d_dir_items,
                     p.d_rings, p.d_ring_four_off, p.d_ring_pair, p.d_ring_q, p.d_fft_items, p.d_passes,
-                    p.d_twid, p.d_four, p.d_fmax};
+                    p.d_twid, p.d_four, p.d_fmax, p.d_diag_e};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &g : p.graphs)
@@ -378,15 +378,21 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         const int rem = smooth_factor(h, f, maxp);
         // Bluestein length: the smallest 2^a 3^b >= 2h - 1 with 9 | L
         // (radix-16/9 passes; the leading radix-9 passes keep the power-of-two
-        // passes' LDS writes off a single bank)
-        int Lb = 2 * h - 1;
-        auto ok23 = [](int x) {
-            int threes = 0;
-            while (x % 2 == 0) x /= 2;
-            while (x % 3 == 0) x /= 3, ++threes;
-            return x == 1 && threes >= 2;
+        // passes' LDS writes off a single bank); if that exceeds the LDS cap
+        // (rings of more than about 7776 points), the smallest such length
+        // that may also hold factors 5 (radix-5 passes), e.g. 8100 for the
+        // longest TCo1999 rings
+        auto smallest = [](int lo, bool fives) {
+            for (int x = lo;; ++x) {
+                int y = x, threes = 0;
+                while (y % 2 == 0) y /= 2;
+                while (y % 3 == 0) y /= 3, ++threes;
+                while (fives && y % 5 == 0) y /= 5;
+                if (y == 1 && threes >= 2) return x;
+            }
         };
-        while (!ok23(Lb)) ++Lb;
+        int Lb = smallest(2 * h - 1, false);
+        if (Lb > cap) Lb = smallest(2 * h - 1, true);
         // one prime factor above the register radices, up to kGpMaxPrime, is
         // run as a general prime pass (first, at Ns = 1) instead of Bluestein
         // when one field's output units fit the block's waves and, above 191,
@@ -397,7 +403,7 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
         // 27.1 ms against the prime pass limited to 191)
         bool gp = rem > 1 && rem <= kGpMaxPrime && is_prime(rem) &&
                   gp_row_tiles(rem) * gp_col_tiles(h / rem) <= kGpUnits * (kFftThreads / 64);
-        if (gp && rem > 191) gp = 3.2 + 0.0086 * rem < 0.37 * Lb / h * std::log2((double)Lb);
+        if (gp && rem > 191 && Lb <= cap) gp = 3.2 + 0.0086 * rem < 0.37 * Lb / h * std::log2((double)Lb);
         if (rem == 1 || gp) {
             lp.L = h;
             lp.blue = 0;
@@ -531,6 +537,7 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
         p.table_bytes *= 2;
     }
     PLAN_TRY(hipMalloc(&p.d_diag, sizeof(double) * (size_t)NL * (N + 1)));
+    PLAN_TRY(hipMalloc(&p.d_diag_e, sizeof(int) * (size_t)NL * (N + 1)));
     PLAN_TRY(hipMalloc(&p.d_mmax, sizeof(unsigned long long) * (N + 1)));
     PLAN_TRY(upload(&p.d_mb, p.mb));
     PLAN_TRY(launch_legendre_tables(p, stream));
@@ -539,6 +546,8 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
     PLAN_TRY(hipMemcpy(p.mb.data(), p.d_mb, sizeof(MBlock) * p.mb.size(), hipMemcpyDeviceToHost));
     (void)hipFree(p.d_diag);
     p.d_diag = nullptr;
+    (void)hipFree(p.d_diag_e);
+    p.d_diag_e = nullptr;
     (void)hipFree(p.d_mmax);
     p.d_mmax = nullptr;
 

@@ -144,7 +144,8 @@ struct Plan {
 
     // Device memory.
     double *d_mu = nullptr, *d_w = nullptr;  // nlat
-    double *d_diag = nullptr;                // [NL][N+1] sectoral seeds (plan time only)
+    double *d_diag = nullptr;                // [NL][N+1] sectoral seeds q (plan time only) ...
+    int *d_diag_e = nullptr;                 // ... and their exponents E: P̄_m^m = q 2^E
     void *d_tab_kr = nullptr, *d_tab_rk = nullptr;        // FP64/FP32 values or BF16 hi
     void *d_tab_kr_lo = nullptr, *d_tab_rk_lo = nullptr;  // BF16 lo
     unsigned long long *d_mmax = nullptr;                  // per-m max |P̄| bits (plan time)

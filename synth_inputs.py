@@ -11,6 +11,7 @@ in m-major order (m = 0..N, n = m..N); the coefficient is
 Band-limited grids for direct-only tests are made by the caller from these
 coefficients; white-noise grids use the same seeding with standard normals.
 """
+import functools
 from dataclasses import dataclass
 
 import numpy as np
@@ -40,13 +41,16 @@ class Workload:
 
 # The five workloads: T79 full 160x320 (1 field, FP64), T255/O256 (411 fields,
 # FP32), TCo639/O640 (411, split BF16), T399/O400 (137, FP32, adjoint),
-# TCo1279/O1280 (411, FP32 and split BF16).
+# TCo1279/O1280 (411, FP32 and split BF16); and the 5 km case the paper runs
+# beyond them, TCo1999/O2000 (4000 latitudes, rings up to 8016 points; 411
+# fields, FP32).
 WORKLOADS = {
     "t79_full": Workload(1, "T79 full Gaussian 160x320", 79, "full", 160, 320, 1, "fp64"),
     "t255_o256": Workload(2, "T255 O256", 255, "octahedral", 512, 0, 411, "fp32"),
     "tco639_o640": Workload(3, "TCo639 O640", 639, "octahedral", 1280, 0, 411, "bf16x3"),
     "t399_o400": Workload(4, "T399 O400", 399, "octahedral", 800, 0, 137, "fp32"),
     "tco1279_o1280": Workload(5, "TCo1279 O1280", 1279, "octahedral", 2560, 0, 411, "fp32"),
+    "tco1999_o2000": Workload(6, "TCo1999 O2000", 1999, "octahedral", 4000, 0, 411, "fp32"),
 }
 
 
@@ -54,11 +58,23 @@ def nspec(trunc: int) -> int:
     return (trunc + 1) * (trunc + 2) // 2
 
 
+@functools.lru_cache(maxsize=8)
 def spec_mn(trunc: int):
-    """(m, n) of every m-major spectral slot."""
+    """(m, n) of every m-major spectral slot (read-only arrays, cached)."""
     m = np.concatenate([np.full(trunc + 1 - mm, mm) for mm in range(trunc + 1)])
     n = np.concatenate([np.arange(mm, trunc + 1) for mm in range(trunc + 1)])
+    m.flags.writeable = False
+    n.flags.writeable = False
     return m, n
+
+
+@functools.lru_cache(maxsize=8)
+def _spectrum(trunc: int):
+    """(n + 1)^-1.5 per slot and the number of m = 0 slots (they come first)."""
+    m, n = spec_mn(trunc)
+    sc = (n + 1.0) ** -1.5
+    sc.flags.writeable = False
+    return sc, trunc + 1
 
 
 def spectral_field(trunc: int, seed: int) -> np.ndarray:
@@ -67,9 +83,11 @@ def spectral_field(trunc: int, seed: int) -> np.ndarray:
     ns = nspec(trunc)
     re = rng.standard_normal(ns)
     im = rng.standard_normal(ns)
-    m, n = spec_mn(trunc)
-    a = (re + 1j * im) * (n + 1.0) ** -1.5
-    a[m == 0] = a[m == 0].real
+    sc, n0 = _spectrum(trunc)
+    im[:n0] = 0.0  # m = 0: real coefficients
+    a = np.empty(ns, dtype=np.complex128)
+    a.real = re * sc
+    a.imag = im * sc
     return a
 
 

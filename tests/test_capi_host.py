@@ -80,13 +80,18 @@ def test_plan_check_all_workloads(lib, prec):
     import synth_inputs as si
     sizes = {"t79_full": (3240, 51200, 12800), "t255_o256": (32896, 271360, 100568),
              "t399_o400": (80200, 654400, 243560), "tco639_o640": (205120, 1661440, 620120),
-             "tco1279_o1280": (819840, 6599680, 2469080)}
+             "tco1279_o1280": (819840, 6599680, 2469080), "tco1999_o2000": (2001000, 16072000, None)}
     for key, w in si.WORKLOADS.items():
-        if key == "tco1279_o1280" and prec != "fp32":
+        if key in ("tco1279_o1280", "tco1999_o2000") and prec != "fp32":
             continue  # same layout code; keep the CPU suite short
         rc, info = shtx.plan_check(w.trunc, w.grid, w.nlat, w.nfld, prec, w.nlon_full)
         assert rc == 0, (key, prec, rc)
-        assert (info.nspec, info.npts, info.nfour) == sizes[key]
+        ns, npts, nfour = sizes[key]
+        assert (info.nspec, info.npts) == (ns, npts)
+        nlon = w.ring_lengths()
+        assert info.nfour == int(sum(min(w.trunc, (int(n) - 1) // 2) + 1 for n in nlon))
+        if nfour is not None:
+            assert info.nfour == nfour
         assert info.table_bytes > 0 and info.legendre_flops > 0
 
 

@@ -80,6 +80,32 @@ def test_legendre_tables(prec, tol):
         assert err < tol, (m, err)
 
 
+def test_legendre_tables_beyond_double_range():
+    """TCo1999 (N = 1999 on O2000) FP64 tables: wavenumbers whose sectoral
+    seeds fall below 1e-310 on many rings while P̄_n^m there reaches order one
+    (up to about 5) match the oracle's extended-exponent columns."""
+    shtx, o = _shtx(), _oracle()
+    N, nlat = 1999, 4000
+    _say(f"tables T{N} O{nlat // 2} fp64 (extended exponent)")
+    plan = shtx.Plan(N, "octahedral", nlat, 1, "fp64")
+    mu, _ = plan.nodes()
+    nlon = plan.ring_lengths()
+    for m in (700, 862, 940):
+        tab = plan.legendre(m)
+        rings = [j for j in range(nlat // 2) if o.ring_cutoff(N, nlon[j]) >= m]
+        ref = o.legendre(N, m, mu[rings])
+        s = np.sqrt((1 - mu[rings]) * (1 + mu[rings]))
+        k = np.arange(1, m + 1)
+        log_seed = np.sum(0.5 * np.log10((2 * k + 1) / (2 * k))) + m * np.log10(s)
+        low = log_seed < -310
+        assert low.any() and np.abs(ref[low]).max() > 1.0, m  # the case is exercised
+        err = np.abs(tab - ref).max() / np.abs(ref).max()
+        _say(f"  m={m}: {int(low.sum())} rings with seeds < 1e-310, max |P| there "
+             f"{np.abs(ref[low]).max():.2f}, error {err:.2e}")
+        assert err < 1e-12, (m, err)
+    plan.close()
+
+
 # ---------------------------------------------------------------------------
 # Transforms on small and multi-tile shapes
 # ---------------------------------------------------------------------------
@@ -301,6 +327,46 @@ def test_tco639_o640_fp16x3_411_fields():
 
 def test_tco1279_o1280_fp16x3_411_fields():
     _full_size("tco1279_o1280", "fp16x3", SAMPLE_16, adjoints=True)
+
+
+def _sampled_size(key, prec, sample):
+    """Like _full_size for a workload too large to generate on the host: the
+    device arrays hold the sampled fields' seeded rows and copies of the
+    first one elsewhere (fields are independent); inverse, direct of the
+    oracle's band-limited grids, and the device round trip, on the samples."""
+    torch, shtx, o = _torch(), _shtx(), _oracle()
+    wl = si.WORKLOADS[key]
+    sample = list(sample)
+    _say(f"{wl.name} {prec}: F={wl.nfld}, sampled fields {sample}")
+    plan = shtx.Plan(wl.trunc, wl.grid, wl.nlat, wl.nfld, prec, nlon_full=wl.nlon_full)
+    nlon = plan.ring_lengths()
+    _, w = o.gauss(wl.nlat)
+    a = si.spectral_fields(wl.trunc, wl.key, sample)
+    spec = _rows_on_device(torch, plan, a, sample, wl.nfld)
+    g_ref = o.inv(wl.trunc, nlon, a)
+    g = _np(plan.inv(spec)[sample])
+    em, er = grid_errors(g, g_ref, nlon, w)
+    _say(f"  inv   e_max {em.max():.2e} e_rms {er.max():.2e}")
+    assert er.max() < TOL_RMS[prec] and em.max() < TOL_MAX[prec]
+    del g
+    b_ref = o.dir(wl.trunc, nlon, g_ref)
+    g_in = _rows_on_device(torch, plan, g_ref, sample, wl.nfld)
+    b = _np(plan.dir(g_in)[sample])
+    del g_in
+    em, er = spec_errors(b, b_ref, wl.trunc)
+    _say(f"  dir   e_max {em.max():.2e} e_rms {er.max():.2e}")
+    assert er.max() < TOL_RMS[prec] and em.max() < TOL_MAX[prec]
+    b = _np(plan.dir(plan.inv(spec))[sample])
+    em, er = spec_errors(b, a, wl.trunc)
+    _say(f"  round trip vs input e_max {em.max():.2e} e_rms {er.max():.2e}")
+    assert er.max() < max(TOL_RMS[prec], 1e-12) * 4
+    plan.close()
+    torch.cuda.synchronize()
+
+
+def test_tco1999_o2000_fp32_411_fields():
+    """The 5 km case (rings up to 8016 points, seeds below the double range)."""
+    _sampled_size("tco1999_o2000", "fp32", [0, 137, 274, 410])
 
 
 def test_tco1279_o1280_fp64_411_fields():
