@@ -44,6 +44,8 @@ def _load():
     lib.oracle_ring_synth.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _f64p, _f64p]
     lib.oracle_ring_dft.argtypes = [ctypes.c_int, ctypes.c_int, _f64p, _f64p]
     lib.oracle_max_threads.restype = ctypes.c_int
+    lib.oracle_legendre_deriv.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _f64p]
+    lib.oracle_uv.argtypes = [ctypes.c_int, ctypes.c_int, _i32p, ctypes.c_int, _f64p, _f64p, _f64p, ctypes.c_int]
     _lib = lib
     return lib
 
@@ -162,3 +164,24 @@ def ring_dft(n: int, M: int, g) -> np.ndarray:
 
 def max_threads() -> int:
     return int(_load().oracle_max_threads())
+
+
+def legendre_deriv(trunc: int, m: int, mu: float) -> np.ndarray:
+    """H_n^m(mu) = (1 - mu^2) dP̄_n^m/dmu for n = m..trunc at one abscissa."""
+    out = np.empty(trunc - m + 1)
+    _load().oracle_legendre_deriv(trunc, m, float(mu), out)
+    return out
+
+
+def uv(trunc, nlon, vor, div, nthreads=0):
+    """Wind images U = u cos(phi), V = v cos(phi) on the unit sphere from
+    spectral vorticity and divergence [nfld, nspec]: grid [2 nfld, npts], U of
+    field f in row f, V in row nfld + f."""
+    nlon, nlat, npts = _geom(nlon)
+    z, nfld = _spec_in(vor, trunc)
+    d, nfld2 = _spec_in(div, trunc)
+    if nfld2 != nfld:
+        raise ValueError("vorticity and divergence hold different field counts")
+    out = np.empty((2 * nfld, npts))
+    _load().oracle_uv(trunc, nlat, nlon, nfld, z, d, out, int(nthreads))
+    return out

@@ -455,3 +455,99 @@ void oracle_dir_adj(int trunc, int nlat, const int32_t *nlon, int nfld,
 }
 
 int oracle_max_threads(void) { return omp_get_max_threads(); }
+
+/* ----------------------------------------------------------------------- */
+/* Wind from vorticity and divergence                                       */
+/* ----------------------------------------------------------------------- */
+
+/* H_n^m(mu) = (1 - mu^2) dP̄_n^m/dmu for n = m .. trunc at one abscissa, from
+ * the derivative identity of the normalised functions
+ *   (1 - mu^2) dP̄_n^m/dmu = -n mu P̄_n^m + (2n + 1) eps_n^m P̄_{n-1}^m,
+ *   eps_n^m = sqrt((n^2 - m^2) / (4 n^2 - 1)),  P̄_{m-1}^m := 0. */
+void oracle_legendre_deriv(int trunc, int m, double mu, double *out)
+{
+    double *p = malloc(sizeof(double) * (trunc - m + 1));
+    double s = sqrt((1.0 - mu) * (1.0 + mu));
+    legendre_column(trunc, m, mu, s, p);
+    for (int n = m; n <= trunc; ++n) {
+        double eps = sqrt(((double)n * n - (double)m * m) / (4.0 * n * n - 1.0));
+        double prev = n > m ? p[n - m - 1] : 0.0;
+        out[n - m] = -n * mu * p[n - m] + (2.0 * n + 1.0) * eps * prev;
+    }
+    free(p);
+}
+
+/* Wind images on the unit sphere from spectral vorticity zeta and divergence
+ * D (truncation trunc, [nfld][nspec] each):
+ *   psi_n^m = -zeta_n^m / (n (n + 1)),  chi_n^m = -D_n^m / (n (n + 1))  (n >= 1;
+ *            0 for n = 0), the streamfunction and velocity potential;
+ *   U = u cos(phi) = d chi / d lambda - (1 - mu^2) d psi / d mu,
+ *   V = v cos(phi) = d psi / d lambda + (1 - mu^2) d chi / d mu,
+ * evaluated as the real fields sum_m c_m Re(X_m(mu_j) e^{i m lambda_k}) with
+ *   U_m(mu) = sum_n (i m chi_n^m P̄_n^m(mu) - psi_n^m H_n^m(mu)),
+ *   V_m(mu) = sum_n (i m psi_n^m P̄_n^m(mu) + chi_n^m H_n^m(mu)),
+ * m <= M_j (ring cutoff of the truncation), Im of the m = 0 coefficients
+ * ignored.  grid is [2 nfld][npts]: U of field f in row f, V in row nfld + f. */
+void oracle_uv(int trunc, int nlat, const int32_t *nlon, int nfld,
+               const double *vor, const double *dvg, double *grid, int nthreads)
+{
+    set_threads(nthreads);
+    double *mu = malloc(sizeof(double) * nlat), *w = malloc(sizeof(double) * nlat);
+    int64_t *off = malloc(sizeof(int64_t) * (nlat + 1));
+    int64_t nspec = oracle_nspec(trunc);
+    oracle_gauss(nlat, mu, w);
+    off[0] = 0;
+    for (int j = 0; j < nlat; ++j) off[j + 1] = off[j] + nlon[j];
+    int64_t npts = off[nlat];
+
+#pragma omp parallel
+    {
+        double *pcol = malloc(sizeof(double) * (trunc + 1));
+        double *hcol = malloc(sizeof(double) * (trunc + 1));
+        double *fu = malloc(sizeof(double) * 2 * (size_t)nfld * (trunc + 1));
+        double *fv = malloc(sizeof(double) * 2 * (size_t)nfld * (trunc + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int j = 0; j < nlat; ++j) {
+            int n_j = nlon[j];
+            int M = oracle_ring_cutoff(trunc, n_j);
+            double x = mu[j], s = sqrt((1.0 - x) * (1.0 + x));
+            for (int m = 0; m <= M; ++m) {
+                legendre_column(trunc, m, x, s, pcol);
+                oracle_legendre_deriv(trunc, m, x, hcol);
+                for (int f = 0; f < nfld; ++f) {
+                    const double *z = vor + 2 * ((int64_t)f * nspec + spec_index(trunc, m, m));
+                    const double *d = dvg + 2 * ((int64_t)f * nspec + spec_index(trunc, m, m));
+                    double ur = 0.0, ui = 0.0, vr = 0.0, vi = 0.0;
+                    for (int n = (m > 0 ? m : 1); n <= trunc; ++n) {
+                        double inv_l = -1.0 / ((double)n * (n + 1));
+                        double psr = inv_l * z[2 * (n - m)], psi = m == 0 ? 0.0 : inv_l * z[2 * (n - m) + 1];
+                        double chr = inv_l * d[2 * (n - m)], chi = m == 0 ? 0.0 : inv_l * d[2 * (n - m) + 1];
+                        double P = pcol[n - m], H = hcol[n - m];
+                        /* i m chi P - psi H */
+                        ur += -m * chi * P - psr * H;
+                        ui += m * chr * P - psi * H;
+                        /* i m psi P + chi H */
+                        vr += -m * psi * P + chr * H;
+                        vi += m * psr * P + chi * H;
+                    }
+                    fu[2 * ((int64_t)f * (trunc + 1) + m)] = ur;
+                    fu[2 * ((int64_t)f * (trunc + 1) + m) + 1] = ui;
+                    fv[2 * ((int64_t)f * (trunc + 1) + m)] = vr;
+                    fv[2 * ((int64_t)f * (trunc + 1) + m) + 1] = vi;
+                }
+            }
+            for (int f = 0; f < nfld; ++f) {
+                oracle_ring_synth(n_j, M, 2.0, fu + 2 * (int64_t)f * (trunc + 1), grid + (int64_t)f * npts + off[j]);
+                oracle_ring_synth(n_j, M, 2.0, fv + 2 * (int64_t)f * (trunc + 1),
+                                  grid + (int64_t)(nfld + f) * npts + off[j]);
+            }
+        }
+        free(pcol);
+        free(hcol);
+        free(fu);
+        free(fv);
+    }
+    free(mu);
+    free(w);
+    free(off);
+}

@@ -445,3 +445,83 @@ def test_workload_geometry():
         assert nl.max() == mx and nl[0] == 20 and nl[-1] == 20
     w = si.WORKLOADS["tco1279_o1280"]
     assert int(w.ring_lengths().sum()) == 6599680
+
+
+# --------------------------------------------------------------------------
+# Wind images from vorticity and divergence
+# --------------------------------------------------------------------------
+
+def test_legendre_deriv_vs_finite_differences():
+    """H_n^m = (1 - mu^2) dP̄_n^m/dmu against a fourth-order central difference
+    of the oracle's own P̄ columns."""
+    o = _orc()
+    N, h = 40, 1e-4
+    for m in (0, 1, 7, 25):
+        for x in (-0.83, 0.05, 0.61):
+            H = o.legendre_deriv(N, m, x)
+            P = [o.legendre(N, m, [x + k * h])[0] for k in (-2, -1, 1, 2)]
+            dP = (P[0] - 8 * P[1] + 8 * P[2] - P[3]) / (12 * h)
+            assert np.max(np.abs(H - (1 - x * x) * dP)) < 1e-8 * max(1.0, np.abs(H).max()), (m, x)
+
+
+def _uv_closed_form_grid(N, nlon, which):
+    o = _orc()
+    mu, _ = o.gauss(len(nlon))
+    ns = o.nspec(N)
+    z = np.zeros((1, ns), complex)
+    d = np.zeros((1, ns), complex)
+    idx = {(0, 1): 1, (1, 1): N + 1}  # m-major index of (m, n) = (0, 1) and (1, 1)
+    lam, mus = [], []
+    for j, n in enumerate(nlon):
+        lam.append(2 * np.pi * np.arange(n) / n)
+        mus.append(np.full(n, mu[j]))
+    lam, x = np.concatenate(lam), np.concatenate(mus)
+    s = np.sqrt((1 - x) * (1 + x))
+    c = np.sqrt(1.5)
+    if which == "rotation":      # zeta_1^0 = 2: U = sqrt(3) (1 - mu^2), V = 0
+        z[0, idx[(0, 1)]] = 2.0
+        U, V = np.sqrt(3) * (1 - x * x), 0 * x
+    elif which == "vortex11":    # zeta_1^1 = 1
+        z[0, idx[(1, 1)]] = 1.0
+        U, V = -c * x * s * np.cos(lam), c * s * np.sin(lam)
+    else:                        # D_1^1 = 1
+        d[0, idx[(1, 1)]] = 1.0
+        U, V = c * s * np.sin(lam), c * x * s * np.cos(lam)
+    return o.uv(N, nlon, z, d), U, V
+
+
+@pytest.mark.parametrize("which", ["rotation", "vortex11", "divergent11"])
+def test_uv_closed_forms(which):
+    """Solid-body rotation and the m = 1 vortex and source: U = u cos(phi) and
+    V = v cos(phi) in closed form, on an octahedral grid with cutoff."""
+    o = _orc()
+    nlon = o.octahedral_nlon(16)
+    g, U, V = _uv_closed_form_grid(15, nlon, which)
+    assert np.max(np.abs(g[0] - U)) < 1e-13
+    assert np.max(np.abs(g[1] - V)) < 1e-13
+
+
+def test_uv_kinetic_energy():
+    """Full Gaussian grid, random band-limited vorticity and divergence: the
+    quadrature of u^2 + v^2 = (U^2 + V^2) / (1 - mu^2) equals
+    sum_{n >= 1} c_m n (n + 1) (|psi_n^m|^2 + |chi_n^m|^2) (exact: the
+    lambda-mean of u^2 + v^2 is a polynomial of degree 2N in mu)."""
+    import synth_inputs as si
+    o = _orc()
+    N, nlat, nl = 31, 64, 128
+    nlon = o.full_nlon(nlat, nl)
+    mu, w = o.gauss(nlat)
+    zeta = si.spectral_fields(N, 91, [0, 1])
+    dvg = si.spectral_fields(N, 92, [0, 1])
+    g = o.uv(N, nlon, zeta, dvg)
+    m, n = si.spec_mn(N)
+    cm = np.where(m == 0, 1.0, 2.0)
+    lap = np.where(n > 0, -1.0 / np.maximum(n * (n + 1), 1), 0.0)
+    for f in range(2):
+        psi, chi = zeta[f] * lap, dvg[f] * lap
+        psi = np.where(m == 0, psi.real, psi)
+        chi = np.where(m == 0, chi.real, chi)
+        rhs = np.sum(cm * n * (n + 1) * (np.abs(psi) ** 2 + np.abs(chi) ** 2))
+        U, V = g[f].reshape(nlat, nl), g[2 + f].reshape(nlat, nl)
+        lhs = 0.5 * np.sum(w[:, None] / nl * (U ** 2 + V ** 2) / (1 - mu[:, None] ** 2))
+        assert abs(lhs - rhs) < 1e-13 * rhs, (f, lhs, rhs)
