@@ -91,6 +91,11 @@ enum shtx_status {
  * architecture, truncation, grid, latitudes, fields, precision and a hash of
  * the kernel sources.  Without the flag each precision uses fixed shapes. */
 #define SHTX_FLAG_AUTOTUNE 4u
+/* Wind images: the plan also serves shtx_uv_trans (it then allocates one more
+ * spectral array of its own shape at create time).  Such a plan has
+ * truncation N + 1 and 2 F fields for F wind fields of truncation N; nfld
+ * must be even and trunc >= 1 (else SHTX_EINVAL). */
+#define SHTX_FLAG_UV 8u
 
 typedef struct {
     int32_t trunc, nlat, nfld, prec, grid;
@@ -165,6 +170,23 @@ int shtx_inv_trans_adj(shtx_plan p, const void *grid_d, void *spec_d, void *hip_
 /* Adjoint of the direct transform: spec -> grid. */
 int shtx_dir_trans_adj(shtx_plan p, const void *spec_d, void *grid_d, void *hip_stream);
 
+/* Wind images from vorticity and divergence (the wind part of the IFS inverse
+ * spectral transform, Section 2.2.2), for a plan made with SHTX_FLAG_UV:
+ * truncation trunc = N + 1, nfld = 2 F.  On the unit sphere, with
+ * streamfunction psi_n^m = -zeta_n^m / (n (n+1)) and velocity potential
+ * chi_n^m = -D_n^m / (n (n+1)) (n >= 1),
+ *   U = u cos(phi) = d chi / d lambda - (1 - mu^2) d psi / d mu,
+ *   V = v cos(phi) = d psi / d lambda + (1 - mu^2) d chi / d mu,
+ * fields of truncation N + 1, evaluated on the plan's grid (the same ring
+ * cutoff and precision form as shtx_inv_trans).  vor_d, div_d: device
+ * [F][(N+1)(N+2)/2] complex each (layout and dtype of the spectral arrays, at
+ * truncation N; Im of the m = 0 coefficients ignored); uv_grid_d: device
+ * [2F][npts] real, U of wind field f in row f and V in row F + f.  The
+ * gradient (d s / d lambda, (1 - mu^2) d s / d mu) of a scalar s is this
+ * transform with zeta = 0 and D_n^m = -n (n+1) s_n^m.  Same checks, errors,
+ * stream semantics and graph replay as the other transforms. */
+int shtx_uv_trans(shtx_plan p, const void *vor_d, const void *div_d, void *uv_grid_d, void *hip_stream);
+
 /* For callers that cannot allocate device memory at transform time (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): shtx_inv_trans with the transform's scratch -- the Fourier
@@ -192,7 +214,8 @@ int shtx_inv_trans_noalloc(shtx_plan p, const void *spec_d, void *grid_d, void *
  * SHTX_EINVAL for a plan made without SHTX_FLAG_TIMING.
  * shtx_timing_read synchronises on the recorded events and returns, per
  * kernel kind, the summed duration in milliseconds and the launch count:
- * index 0 inverse-shaped Legendre GEMM (inv_trans, dir_trans_adj),
+ * index 0 inverse-shaped Legendre GEMM (inv_trans, dir_trans_adj, and
+ * uv_trans with its spectral wind step),
  * 1 direct-shaped Legendre GEMM (dir_trans, inv_trans_adj), 2 ring c2r FFT,
  * 3 ring r2c FFT.  Both arrays have 4 entries; either may be NULL.  At most
  * 4096 launches are recorded between resets; later ones are not timed. */

@@ -25,12 +25,13 @@ PRECS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 FLAG_GRAPH = 1
 FLAG_TIMING = 2
 FLAG_AUTOTUNE = 4
+FLAG_UV = 8
 
 _lib = None
 
 _EXPORTS = ("shtx_plan_create", "shtx_plan_check", "shtx_plan_check_shapes", "shtx_plan_set_shapes", "shtx_plan_info", "shtx_plan_ring_lengths", "shtx_plan_nodes",
             "shtx_plan_legendre", "shtx_inv_trans", "shtx_dir_trans", "shtx_inv_trans_adj",
-            "shtx_dir_trans_adj", "shtx_inv_trans_noalloc", "shtx_timing_reset", "shtx_timing_enable", "shtx_timing_read", "shtx_plan_destroy",
+            "shtx_dir_trans_adj", "shtx_uv_trans", "shtx_inv_trans_noalloc", "shtx_timing_reset", "shtx_timing_enable", "shtx_timing_read", "shtx_plan_destroy",
             "shtx_strerror")
 
 
@@ -68,6 +69,7 @@ def load_library():
     for name in ("shtx_inv_trans", "shtx_dir_trans", "shtx_inv_trans_adj", "shtx_dir_trans_adj",
                  "shtx_inv_trans_noalloc"):
         getattr(lib, name).argtypes = [vp, vp, vp, vp]
+    lib.shtx_uv_trans.argtypes = [vp, vp, vp, vp, vp]
     lib.shtx_timing_reset.argtypes = [vp]
     lib.shtx_timing_enable.argtypes = [vp, i32]
     lib.shtx_timing_read.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
@@ -111,7 +113,7 @@ class Plan:
     the current CUDA/HIP device.  Transforms run on torch's current stream."""
 
     def __init__(self, trunc, grid="octahedral", nlat=None, nfld=1, prec="fp32", nlon_full=0,
-                 graph=False, timing=False, autotune=False):
+                 graph=False, timing=False, autotune=False, uv=False):
         import torch
         if not torch.cuda.is_available():
             raise ShtxError("libshtx needs a ROCm GPU; no CPU fallback exists")
@@ -119,7 +121,8 @@ class Plan:
         if nlat is None:
             nlat = 2 * (trunc + 1)
         self.trunc, self.grid, self.nlat, self.nfld, self.prec = trunc, grid, nlat, nfld, prec
-        flags = (FLAG_GRAPH if graph else 0) | (FLAG_TIMING if timing else 0) | (FLAG_AUTOTUNE if autotune else 0)
+        flags = ((FLAG_GRAPH if graph else 0) | (FLAG_TIMING if timing else 0) | (FLAG_AUTOTUNE if autotune else 0)
+                 | (FLAG_UV if uv else 0))
         h = ctypes.c_void_p()
         stream = torch.cuda.current_stream().cuda_stream
         _check(lib.shtx_plan_create(ctypes.byref(h), trunc, GRIDS[grid], nlat, nlon_full, nfld,
@@ -202,6 +205,25 @@ class Plan:
     def inv(self, spec, out=None):
         """Inverse transform: spectral [nfld, nspec] -> grid [nfld, npts]."""
         return self._run("shtx_inv_trans", spec, "spec", "grid", out)
+
+    def uv(self, vor, div, out=None):
+        """Wind images U = u cos(phi), V = v cos(phi) from vorticity and
+        divergence (plans made with uv=True: truncation N + 1, 2 F fields):
+        vor, div [F, (N+1)(N+2)/2] complex -> grid [2 F, npts], U rows first."""
+        import torch
+        F, nsw = self.nfld // 2, self.trunc * (self.trunc + 1) // 2
+        xs = []
+        for x in (vor, div):
+            if not x.is_cuda or x.dtype != self.complex_dtype or tuple(x.shape) != (F, nsw):
+                raise ShtxError(f"wind inputs must be device {self.complex_dtype} [{F}, {nsw}], "
+                                f"got {x.dtype} {tuple(x.shape)} on {x.device}")
+            xs.append(x.contiguous())
+        y = self._out("grid", out, xs[0].device)
+        stream = torch.cuda.current_stream(xs[0].device).cuda_stream
+        _check(load_library().shtx_uv_trans(self._h, ctypes.c_void_p(xs[0].data_ptr()),
+                                            ctypes.c_void_p(xs[1].data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                            ctypes.c_void_p(stream)), "shtx_uv_trans")
+        return y
 
     def inv_noalloc(self, spec, out):
         """Inverse transform through shtx_inv_trans_noalloc: the library's static

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libshtx.so")
-SOURCES = ["plan.cpp", "capi.cpp", "autotune.cpp", "k_tables.hip", "k_gemm.hip", "k_fft.hip"]
+SOURCES = ["plan.cpp", "capi.cpp", "autotune.cpp", "k_tables.hip", "k_gemm.hip", "k_fft.hip", "k_wind.hip"]
 BUILD = os.path.join(HERE, "_build")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-I", INCLUDE,

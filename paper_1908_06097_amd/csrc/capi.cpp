@@ -63,10 +63,21 @@ hipError_t mark_done(Plan &p, hipStream_t s)
 // Wait for the last recorded transform of the plan.
 hipError_t wait_done(Plan &p) { return p.done ? hipEventSynchronize(p.done) : hipSuccess; }
 
-// Argument checks shared by every transform entry point.
-int check_args(const Plan &p, int kind, const void *in, const void *out)
+// Argument checks shared by every transform entry point (in2: the wind
+// transform's second input).
+int check_args(const Plan &p, int kind, const void *in, const void *out, const void *in2)
 {
     if (!in || !out || !p.shapes_ok) return SHTX_EINVAL;
+    if (kind == kWind) {
+        // vorticity and divergence at truncation trunc - 1, nfld / 2 fields each
+        if (!in2 || !p.d_uvspec) return SHTX_EINVAL;
+        const size_t nwin = (size_t)(p.nfld / 2) * p.trunc * (p.trunc + 1) / 2 * (p.prec == SHTX_FP64 ? 16 : 8);
+        if (overlap(in, nwin, out, grid_bytes(p)) || overlap(in2, nwin, out, grid_bytes(p))) return SHTX_EINVAL;
+        if (!aligned16(in) || !aligned16(in2) || !aligned16(out)) return SHTX_EINVAL;
+        if (!device_memory(in, p.device) || !device_memory(in2, p.device) || !device_memory(out, p.device))
+            return SHTX_EINVAL;
+        return SHTX_OK;
+    }
     bool spec_in = kind == kInverse || kind == kDirectAdj;
     size_t nin = spec_in ? spec_bytes(p) : grid_bytes(p);
     size_t nout = spec_in ? grid_bytes(p) : spec_bytes(p);
@@ -93,7 +104,8 @@ int hip_status(hipError_t e)
 }
 
 // Launch the kernels of one transform kind on stream s.
-hipError_t launch_kind(Plan &p, int kind, const void *in, void *out, hipStream_t s, bool timed)
+hipError_t launch_kind(Plan &p, int kind, const void *in, void *out, hipStream_t s, bool timed,
+                       const void *in2 = nullptr)
 {
     hipError_t e = hipSuccess;
     auto timed_launch = [&](int tkind, auto &&fn) -> hipError_t {
@@ -126,6 +138,14 @@ hipError_t launch_kind(Plan &p, int kind, const void *in, void *out, hipStream_t
         e = timed_launch(3, [&] { return shtx::launch_fft_r2c(p, in, p.d_four, true, p.d_fmax, s); });
         if (e == hipSuccess) e = timed_launch(1, [&] { return shtx::launch_gemm_direct(p, p.d_four, out, true, p.d_fmax, s); });
         break;
+    case shtx::kWind:
+        // the wind step is timed with the inverse-shaped GEMM it feeds
+        e = timed_launch(0, [&] {
+            hipError_t r = shtx::launch_uv_spec(p, in, in2, p.d_uvspec, s);
+            return r != hipSuccess ? r : shtx::launch_gemm_inverse(p, p.d_uvspec, p.d_four, p.d_fmax, s);
+        });
+        if (e == hipSuccess) e = timed_launch(2, [&] { return shtx::launch_fft_c2r(p, p.d_four, out, false, s); });
+        break;
     default:
         e = hipErrorInvalidValue;
     }
@@ -133,23 +153,23 @@ hipError_t launch_kind(Plan &p, int kind, const void *in, void *out, hipStream_t
 }
 
 
-int run(shtx_plan h, int kind, const void *in, void *out, void *stream)
+int run(shtx_plan h, int kind, const void *in, void *out, void *stream, const void *in2 = nullptr)
 {
     if (!h) return SHTX_EINVAL;
     Plan &p = h->p;
-    int rc = check_args(p, kind, in, out);
+    int rc = check_args(p, kind, in, out, in2);
     if (rc != SHTX_OK) return rc;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     bool timed = p.timing_on;
     bool graph = (p.flags & SHTX_FLAG_GRAPH) != 0 && !timed && s != nullptr;
     if (!graph) {
-        hipError_t e = launch_kind(p, kind, in, out, s, timed);
+        hipError_t e = launch_kind(p, kind, in, out, s, timed, in2);
         if (e == hipSuccess) e = mark_done(p, s);
         return hip_status(e);
     }
 
     Plan::GraphEntry &g = p.graphs[kind];
-    if (!(g.exec && g.in == in && g.out == out && g.stream == s)) {
+    if (!(g.exec && g.in == in && g.in2 == in2 && g.out == out && g.stream == s)) {
         if (g.exec) {
             (void)hipGraphExecDestroy(g.exec);
             g.exec = nullptr;
@@ -157,7 +177,7 @@ int run(shtx_plan h, int kind, const void *in, void *out, void *stream)
         hipGraph_t graph_obj = nullptr;
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_status(e);
-        hipError_t le = launch_kind(p, kind, in, out, s, false);
+        hipError_t le = launch_kind(p, kind, in, out, s, false, in2);
         e = hipStreamEndCapture(s, &graph_obj);
         if (le != hipSuccess || e != hipSuccess) {
             if (graph_obj) (void)hipGraphDestroy(graph_obj);
@@ -170,6 +190,7 @@ int run(shtx_plan h, int kind, const void *in, void *out, void *stream)
             return hip_status(e);
         }
         g.in = in;
+        g.in2 = in2;
         g.out = out;
         g.stream = s;
     }
@@ -357,6 +378,11 @@ int shtx_plan_legendre(shtx_plan h, int m, double *out)
 int shtx_inv_trans(shtx_plan h, const void *spec, void *grid, void *stream)
 {
     return run(h, shtx::kInverse, spec, grid, stream);
+}
+
+int shtx_uv_trans(shtx_plan h, const void *vor, const void *dvg, void *grid, void *stream)
+{
+    return run(h, shtx::kWind, vor, grid, stream, dvg);
 }
 
 int shtx_inv_trans_noalloc(shtx_plan h, const void *spec, void *grid, void *stream)

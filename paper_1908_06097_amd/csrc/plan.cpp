@@ -159,7 +159,7 @@ void free_plan(Plan &p)
     void *ptrs[] = {p.d_mu, p.d_w, p.d_diag, p.d_tab_kr, p.d_tab_rk, p.d_tab_kr_lo,
                     p.d_tab_rk_lo, p.d_mmax, p.d_mb, p.d_inv_items, p.d_dir_items,
                     p.d_rings, p.d_ring_four_off, p.d_ring_pair, p.d_ring_q, p.d_fft_items, p.d_passes,
-                    p.d_twid, p.d_four, p.d_fmax, p.d_diag_e};
+                    p.d_twid, p.d_four, p.d_fmax, p.d_diag_e, p.d_uvspec};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (auto &g : p.graphs)
@@ -302,6 +302,8 @@ int plan_layout(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld,
     if (nlat % 2) return SHTX_EUNSUPPORTED;
     if (grid == SHTX_GRID_FULL && (nlon_full < 2 || nlon_full % 2)) return nlon_full < 2 ? SHTX_EINVAL : SHTX_EUNSUPPORTED;
     if (trunc > 4095 || nlat > 16384 || nfld > (1 << 20)) return SHTX_EUNSUPPORTED;
+    // wind images: truncation N + 1 >= 1 and fields U then V
+    if ((flags & SHTX_FLAG_UV) && (trunc < 1 || nfld % 2)) return SHTX_EINVAL;
 
     p.trunc = trunc;
     p.grid = grid;
@@ -604,6 +606,10 @@ int build_plan(Plan &p, int trunc, int grid, int nlat, int nlon_full, int nfld, 
     PLAN_TRY(hipEventCreateWithFlags(&p.done, hipEventDisableTiming));
 
     PLAN_TRY(hipMalloc(&p.d_four, (size_t)p.nfour * nfld * celem));
+    if (flags & SHTX_FLAG_UV) {
+        PLAN_TRY(hipMalloc(&p.d_uvspec, (size_t)p.nspec * nfld * celem));
+        p.workspace_bytes += (size_t)p.nspec * nfld * celem;
+    }
 
     if (flags & SHTX_FLAG_AUTOTUNE) {
         int trc = autotune_plan(p, stream);

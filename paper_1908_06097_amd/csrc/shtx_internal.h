@@ -106,7 +106,8 @@ struct FftItem {
     int ring, f0, nf, pad_;
 };
 
-enum TransformKind { kInverse = 0, kDirect = 1, kInverseAdj = 2, kDirectAdj = 3 };
+enum TransformKind { kInverse = 0, kDirect = 1, kInverseAdj = 2, kDirectAdj = 3, kWind = 4 };
+constexpr int kKinds = 5;
 
 // The split-precision forms: hi + lo halves of bfloat16 or IEEE half.
 inline bool split_form(int prec) { return prec == SHTX_BF16X3 || prec == SHTX_FP16X3; }
@@ -164,6 +165,9 @@ struct Plan {
     // SHTX_FP16X3: per field, the largest magnitude (float bits) of the data
     // the next Legendre GEMM splits (spectral input or Fourier workspace)
     unsigned *d_fmax = nullptr;
+    // SHTX_FLAG_UV: spectral wind images [nfld][nspec] (U then V) between the
+    // wind step and the inverse transform
+    void *d_uvspec = nullptr;
     double qmax = 0.0;  // max over northern rings of w_j / 2
     int64_t tab_elems = 0;   // elements per table layout
     size_t table_bytes = 0, workspace_bytes = 0;
@@ -173,10 +177,10 @@ struct Plan {
     // Graph cache (one per transform kind, keyed on pointers and stream).
     struct GraphEntry {
         hipGraphExec_t exec = nullptr;
-        const void *in = nullptr;
+        const void *in = nullptr, *in2 = nullptr;
         void *out = nullptr;
         hipStream_t stream = nullptr;
-    } graphs[4];
+    } graphs[kKinds];
 
     // Kernel timing.
     static constexpr int kMaxTimed = 4096;
@@ -190,7 +194,7 @@ inline int grid_elem_bytes(int prec) { return prec == SHTX_FP64 ? 8 : 4; }
 
 // Transform-call helpers of the C ABI (capi.cpp): argument checks (SHTX_OK or
 // SHTX_EINVAL, nothing launched), and the per-plan completion event.
-int check_args(const Plan &p, int kind, const void *in, const void *out);
+int check_args(const Plan &p, int kind, const void *in, const void *out, const void *in2 = nullptr);
 hipError_t mark_done(Plan &p, hipStream_t s);
 hipError_t wait_done(Plan &p);
 
@@ -206,6 +210,9 @@ hipError_t launch_fft_c2r(const Plan &p, const void *four, void *grid, bool adjo
                           hipStream_t s);
 hipError_t launch_fft_r2c(const Plan &p, const void *grid, void *four, bool adjoint, unsigned *fmax,
                           hipStream_t s);
+// Wind step of shtx_uv_trans: spectral vorticity and divergence of truncation
+// trunc - 1 (nfld / 2 fields each) -> spectral U and V of truncation trunc.
+hipError_t launch_uv_spec(const Plan &p, const void *vor, const void *dvg, void *out, hipStream_t s);
 // Fields per ring-FFT block are at most this many when the r2c kernel also
 // records each field's largest output magnitude (SHTX_FP16X3 plans).
 constexpr int kFmaxFields = 1024;

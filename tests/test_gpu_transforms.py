@@ -202,6 +202,68 @@ def test_t79_full_fp64_round_trip():
 
 
 # ---------------------------------------------------------------------------
+# Wind images from vorticity and divergence
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("shape", ["T31_O32_F3", "T159_O160_F35", "T63_full_F2"])
+def test_uv_parity(prec, shape):
+    """U = u cos(phi) and V = v cos(phi) from random band-limited vorticity and
+    divergence against the oracle (a plan of truncation N + 1, 2 F fields)."""
+    torch, shtx, o = _torch(), _shtx(), _oracle()
+    if shape == "T31_O32_F3":
+        N, grid, nlat, nl_full, F = 31, "octahedral", 64, 0, 3
+    elif shape == "T159_O160_F35":
+        N, grid, nlat, nl_full, F = 159, "octahedral", 320, 0, 35
+    else:
+        N, grid, nlat, nl_full, F = 63, "full", 64, 130, 2
+    _say(f"uv {shape} {prec}")
+    plan = shtx.Plan(N + 1, grid, nlat, 2 * F, prec, nlon_full=nl_full, uv=True)
+    nlon = plan.ring_lengths()
+    _, w = o.gauss(nlat)
+    zeta = si.spectral_fields(N, 61, range(F))
+    dvg = si.spectral_fields(N, 62, range(F))
+    ref = o.uv(N, nlon, zeta, dvg)
+    g = _np(plan.uv(_dev(zeta, plan.complex_dtype), _dev(dvg, plan.complex_dtype)))
+    em, er = grid_errors(g, ref, nlon, w)
+    _say(f"  U,V e_max {em.max():.2e} e_rms {er.max():.2e}")
+    assert er.max() < TOL_RMS[prec] and em.max() < TOL_MAX[prec]
+    plan.close()
+
+
+def test_uv_graph_replay_and_gradient():
+    """The wind transform replays as a graph; with zeta = 0 and D = -n(n+1) s it
+    gives the gradient (d s/d lambda, (1 - mu^2) d s/d mu) of a scalar s, which
+    for s = P̄_2^0 = (sqrt(5)/2)(3 mu^2 - 1) is (0, 3 sqrt(5) mu (1 - mu^2))."""
+    torch, shtx, o = _torch(), _shtx(), _oracle()
+    N, F = 31, 2
+    plan = shtx.Plan(N + 1, "octahedral", 64, 2 * F, "fp64", uv=True, graph=True)
+    ns = si.nspec(N)
+    s_spec = np.zeros((F, ns), complex)
+    s_spec[:, 2] = 1.0  # (m, n) = (0, 2)
+    m_, n_ = si.spec_mn(N)
+    dvg = -(n_ * (n_ + 1))[None, :] * s_spec
+    zeta = np.zeros_like(dvg)
+    mu, _ = plan.nodes()
+    nlon = plan.ring_lengths()
+    x = np.repeat(mu, nlon)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        vz, vd = _dev(zeta, torch.complex128), _dev(dvg, torch.complex128)
+        out = torch.empty((2 * F, plan.npts), dtype=torch.float64, device="cuda")
+        for rep in range(3):
+            out.fill_(float("nan"))
+            plan.uv(vz, vd, out=out)
+            side.synchronize()
+            g = _np(out)
+            assert np.max(np.abs(g[:F])) < 1e-13, rep
+            V = 3 * np.sqrt(5) * x * (1 - x * x)
+            assert np.max(np.abs(g[F:] - V[None, :])) < 1e-13, rep
+    torch.cuda.synchronize()
+    plan.close()
+
+
+# ---------------------------------------------------------------------------
 # Full-size workloads on sampled fields
 # ---------------------------------------------------------------------------
 
