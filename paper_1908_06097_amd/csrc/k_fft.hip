@@ -10,10 +10,13 @@
 // always up to 191, above that where the plan's cost model prefers it to
 // Bluestein) runs as a general prime pass on the matrix cores (below); other
 // lengths go through Bluestein's chirp convolution at a length L = 2^a 3^b
-// >= 2h - 1, with the filter spectrum precomputed per ring length at plan
-// time.  Only the kept wavenumbers
-// m <= M_j are read or written; they live in the Fourier workspace laid out
-// [ring][m][field], so a block's loads and stores are runs over fields.
+// >= 2h - 1 (2^a 3^b 5^c when that exceeds the LDS cap), with the filter
+// spectrum precomputed per ring length at plan time.  Only the kept
+// wavenumbers m <= M_j are read or written; they live in the Fourier
+// workspace laid out [ring][m][field], so a block's loads and stores are runs
+// over fields.  For the split IEEE-half Legendre form the r2c kernel also
+// records each field's largest output magnitude (the bound from which the
+// direct GEMM scales its data operand).
 //
 // Inverse (c2r):  g_k = s_j * (Re Y_0 + 2 sum_{m=1}^{M} Re(Y_m e^{2 pi i m k / n}))
 //   transform:            Y_m = F_m,                    s_j = 1
