@@ -962,7 +962,7 @@ int gemm_tile_candidates(int prec, int *bm, int *bn, int max)
 {
     static const int f32[][2] = {{128, 128}, {64, 128}, {128, 64}};
     static const int f64[][2] = {{64, 64}, {32, 64}, {64, 32}};
-    static const int b16[][2] = {{128, 128}, {64, 128}};
+    static const int b16[][2] = {{64, 128}, {128, 128}};
     const int(*t)[2] = prec == SHTX_FP64 ? f64 : prec == SHTX_FP32 ? f32 : b16;
     int n = split_form(prec) ? 2 : 3;
     for (int i = 0; i < n && i < max; ++i) {

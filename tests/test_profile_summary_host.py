@@ -19,7 +19,8 @@ def test_classify_gemm_instantiations():
     assert rs.classify(f"void {NS}k_leg_mfma<double, 64, 32, 16, false, 4>{args}") == "legendre_direct_gemm"
     assert rs.classify(f"void {NS}k_leg_split<false, 64, 128, 32, true>{args}") == "legendre_inverse_gemm"
     assert rs.classify(f"void {NS}k_leg_split<true, 128, 128, 32, false>{args}") == "legendre_direct_gemm"
-    # the split-half form's spectral maximum runs in the inverse-shaped GEMM stage
+    # the split-half form's spectral maximum and the wind step run in the inverse-shaped GEMM stage
+    assert rs.classify(f"void {NS}k_uv_spec<float>({NS}Cx<float> const*)") == "legendre_inverse_gemm"
     assert rs.classify(f"void {NS}k_spec_absmax(float2 const*, long, int, unsigned int*)") == "legendre_inverse_gemm"
 
 
