@@ -419,18 +419,29 @@ typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 // memory instructions need only 4-byte alignment)
 typedef float f32x4a8 __attribute__((ext_vector_type(4), aligned(8)));
 
+// lo = x - hi must be taken against the very hi that is stored.  Left to
+// itself the compiler re-derives hi for that subtraction from the product
+// that produced x, by another instruction (a mixed-precision FMA rounding the
+// exact product to half once) whose result differs from the stored hi
+// wherever the two roundings disagree; hi + lo is then off by a unit of hi.
+// An empty asm statement makes the stored hi's bits opaque, so the residual
+// is computed from them.
 template <bool F16>
 __device__ inline void split2(float x0, float x1, unsigned &hi, unsigned &lo)
 {
     if constexpr (F16) {
-        const f16x2 h = {(_Float16)x0, (_Float16)x1};
+        unsigned hb = __builtin_bit_cast(unsigned, f16x2{(_Float16)x0, (_Float16)x1});
+        asm("" : "+v"(hb));
+        const f16x2 h = __builtin_bit_cast(f16x2, hb);
         const f16x2 l = {(_Float16)(x0 - (float)h[0]), (_Float16)(x1 - (float)h[1])};
-        hi = __builtin_bit_cast(unsigned, h);
+        hi = hb;
         lo = __builtin_bit_cast(unsigned, l);
     } else {
-        const bf16x2 h = {(__bf16)x0, (__bf16)x1};
+        unsigned hb = __builtin_bit_cast(unsigned, bf16x2{(__bf16)x0, (__bf16)x1});
+        asm("" : "+v"(hb));
+        const bf16x2 h = __builtin_bit_cast(bf16x2, hb);
         const bf16x2 l = {(__bf16)(x0 - (float)h[0]), (__bf16)(x1 - (float)h[1])};
-        hi = __builtin_bit_cast(unsigned, h);
+        hi = hb;
         lo = __builtin_bit_cast(unsigned, l);
     }
 }

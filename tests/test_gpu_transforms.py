@@ -3,8 +3,8 @@
 Every call goes through the C ABI (via the thin Python binding).  Inputs are
 the seeded synthetic spectra of ``synth_inputs``; expected values come only
 from ``oracle``.  Tolerances: FP64 1e-12 (max relative), FP32 1e-5 (RMS),
-split BF16 and split IEEE half 1e-4 (RMS), per field, on spectral and grid
-outputs.
+split BF16 1e-4 (RMS), split IEEE half 2e-6 (RMS), per field, on spectral
+and grid outputs.
 """
 import numpy as np
 import pytest
@@ -14,8 +14,11 @@ from error_metrics import grid_errors, spec_errors
 
 pytestmark = pytest.mark.gpu
 
-TOL_RMS = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4, "fp16x3": 1e-4}
-TOL_MAX = {"fp64": 1e-12, "fp32": 1e-4, "bf16x3": 1e-3, "fp16x3": 1e-3}
+# split IEEE half keeps 22 of FP32's 24 significand bits on every operand,
+# so its bound is set well inside FP32's: an inexact split (a hi and lo that
+# do not sum to the operand) shows up at 1e-5 and above
+TOL_RMS = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4, "fp16x3": 2e-6}
+TOL_MAX = {"fp64": 1e-12, "fp32": 1e-4, "bf16x3": 1e-3, "fp16x3": 1e-5}
 
 
 def _torch():
