@@ -488,11 +488,19 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
     constexpr int LDK = BK + 8;  // 16-byte aligned rows, staggered banks
     constexpr int CH = BK / 8;   // 16-byte chunks per tile row
     constexpr int NA = (2 * 2 * BM * CH) / 256;  // table chunk loads per thread
-    // operand units: INV (field, 16 consecutive n = 8 k of each parity),
-    // DIR (field, 8 consecutive rings, north and south)
+    // DIR operand units: (field, 8 consecutive rings, north and south)
     constexpr int NUNIT = (BN / 2) * CH;
     constexpr int NU = (NUNIT + 255) / 256;
     static_assert(NA * 256 == 2 * 2 * BM * CH, "table tile must split evenly");
+    // INV operand chunks: 4 consecutive n (two kappa of each parity) of one
+    // field, 32 bytes; the JC chunks of a field's stage are taken by JC
+    // consecutive lanes, so four lanes share each 128-byte line and one load
+    // instruction of a wave touches 16 lines (one line per lane when each
+    // lane read a whole run of 16 n)
+    constexpr int JC = BK / 2;
+    constexpr int NIU = (BN / 2) * JC / 256;
+    static_assert(!INVERSE || (NIU * 256 == (BN / 2) * JC && 4 * NIU <= 16 * NU),
+                  "inverse operand chunks must split evenly");
     // operand tiles As[p][h][i][kappa], Bs[p][h][j][kappa]; the direct form
     // reuses the same LDS to stage its output tile
     constexpr int NSMEM16 = 2 * 2 * (BM + BN) * LDK;
@@ -532,6 +540,17 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
         if constexpr (F16) {
             const int f = col0 / 2 + ufl[u];
             if (uon[u] && f < a.nfld) usc[u] = ldexpf(1.f, field_exp(a.fmax, f, a.dbound));
+        }
+    }
+    // INV: the fields of this thread's chunks and their data scales
+    const int ij = tid % JC;
+    float isc[NIU];
+#pragma unroll
+    for (int u = 0; u < NIU; ++u) {
+        isc[u] = 1.f;
+        if constexpr (F16 && INVERSE) {
+            const int f = col0 / 2 + (u * 256 + tid) / JC;
+            if (f < a.nfld) isc[u] = ldexpf(1.f, field_exp(a.fmax, f, a.dbound));
         }
     }
 
@@ -575,28 +594,29 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
             ra[v] = *reinterpret_cast<const u32x4 *>((hl ? Tl : Th) + p * pstride + (int64_t)(row0 + i) * lda + kk +
                                                      ch * 8);
         }
+        const float2 zero = {0.f, 0.f};
+        if constexpr (INVERSE) {
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            const int idx = tid + u * 256;
-            const float2 zero = {0.f, 0.f};
-            if (INVERSE) {
-                // 16 consecutive n = m + 2 kk + 16 qc + t of one field: parity t & 1, k = kk + 8 qc + t / 2
-                const int qc = idx % CH, f = col0 / 2 + ufl[u];
-                const int nrel0 = 2 * kk + 16 * qc;
-                const float2 *src = (const float2 *)a.in + (int64_t)f * a.nspec + sb + nrel0;
-                if (uon[u] && f < a.nfld && m + nrel0 + 15 <= a.trunc) {
-#pragma unroll
-                    for (int t = 0; t < 8; ++t) {
-                        const f32x4a8 v4 = *reinterpret_cast<const f32x4a8 *>(src + 2 * t);
-                        rv[u][2 * t] = float2{v4[0], v4[1]};
-                        rv[u][2 * t + 1] = float2{v4[2], v4[3]};
-                    }
+            for (int u = 0; u < NIU; ++u) {
+                const int f = col0 / 2 + (u * 256 + tid) / JC;
+                const int nrel = 2 * kk + 4 * ij;
+                const float2 *src = (const float2 *)a.in + (int64_t)f * a.nspec + sb + nrel;
+                if (f < a.nfld && m + nrel + 3 <= a.trunc) {
+                    const f32x4a8 v0 = *reinterpret_cast<const f32x4a8 *>(src);
+                    const f32x4a8 v1 = *reinterpret_cast<const f32x4a8 *>(src + 2);
+                    rv[0][4 * u] = float2{v0[0], v0[1]};
+                    rv[0][4 * u + 1] = float2{v0[2], v0[3]};
+                    rv[0][4 * u + 2] = float2{v1[0], v1[1]};
+                    rv[0][4 * u + 3] = float2{v1[2], v1[3]};
                 } else {
 #pragma unroll
-                    for (int t = 0; t < 16; ++t)
-                        rv[u][t] = (uon[u] && f < a.nfld && m + nrel0 + t <= a.trunc) ? src[t] : zero;
+                    for (int t = 0; t < 4; ++t)
+                        rv[0][4 * u + t] = (f < a.nfld && m + nrel + t <= a.trunc) ? src[t] : zero;
                 }
-            } else {
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
                 // 8 consecutive rings of one field, north and south; the
                 // rings' offsets come from the previous stage's meta fetch
                 const int f = col0 / 2 + ufl[u];
@@ -624,30 +644,34 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
             int i = rem / CH, ch = rem - i * CH;
             *reinterpret_cast<u32x4 *>(&As[p][hl][i][ch * 8]) = ra[v];
         }
+        if constexpr (INVERSE) {
+            // chunk u holds n = 4 ij + t (t = 0..3): kappa 2 ij + t / 2 of parity t & 1
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            if (!uon[u]) continue;
-            const int idx = tid + u * 256;
-            const float sc = usc[u];
-            float x[8];
-            u32x4 hi, lo;
-            if (INVERSE) {
-                const int fl = ufl[u], qc = idx % CH;
+            for (int u = 0; u < NIU; ++u) {
+                const int fl = (u * 256 + tid) / JC;
+                const float sc = isc[u];
+                unsigned hi, lo;
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) x[q] = rv[u][2 * q + p].x * sc;
-                    split8<F16>(x, hi, lo);
-                    *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * fl][qc * 8]) = hi;
-                    *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * fl][qc * 8]) = lo;
+                    split2<F16>(rv[0][4 * u + p].x * sc, rv[0][4 * u + 2 + p].x * sc, hi, lo);
+                    *reinterpret_cast<unsigned *>(&Bs[p][0][2 * fl][2 * ij]) = hi;
+                    *reinterpret_cast<unsigned *>(&Bs[p][1][2 * fl][2 * ij]) = lo;
                     // Im a^0_n is ignored
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) x[q] = m == 0 ? 0.f : rv[u][2 * q + p].y * sc;
-                    split8<F16>(x, hi, lo);
-                    *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * fl + 1][qc * 8]) = hi;
-                    *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * fl + 1][qc * 8]) = lo;
+                    const float y0 = m == 0 ? 0.f : rv[0][4 * u + p].y * sc;
+                    const float y1 = m == 0 ? 0.f : rv[0][4 * u + 2 + p].y * sc;
+                    split2<F16>(y0, y1, hi, lo);
+                    *reinterpret_cast<unsigned *>(&Bs[p][0][2 * fl + 1][2 * ij]) = hi;
+                    *reinterpret_cast<unsigned *>(&Bs[p][1][2 * fl + 1][2 * ij]) = lo;
                 }
-            } else {
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                if (!uon[u]) continue;
+                const int idx = tid + u * 256;
+                const float sc = usc[u];
+                float x[8];
+                u32x4 hi, lo;
                 // hemispheric fold: parity 0 takes q (north + south), parity 1 q (north - south)
                 const int cp = ufl[u], rc = idx / (BN / 2);
 #pragma unroll
