@@ -481,25 +481,29 @@ __device__ inline int field_exp(const unsigned *fmax, int f, float bound)
     return 14 - X;
 }
 
-template <bool F16, int BM, int BN, int BK, bool INVERSE>
-__global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
+template <bool F16, int BM, int BN, int BK, bool INVERSE, int NW>
+__global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
 {
-    constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+    // NW waves as 2 x (NW / 2): rows split in two, columns in NW / 2
+    constexpr int NT = 64 * NW, NWN = NW / 2;
+    constexpr int WM = BM / 2, WN = BN / NWN, FM = WM / 16, FN = WN / 16;
+    static_assert(NW == 4 || NW == 8, "4 or 8 waves per block");
     constexpr int LDK = BK + 8;  // 16-byte aligned rows, staggered banks
     constexpr int CH = BK / 8;   // 16-byte chunks per tile row
-    constexpr int NA = (2 * 2 * BM * CH) / 256;  // table chunk loads per thread
+    constexpr int NA = (2 * 2 * BM * CH) / NT;  // table chunk loads per thread
     // DIR operand units: (field, 8 consecutive rings, north and south)
     constexpr int NUNIT = (BN / 2) * CH;
-    constexpr int NU = (NUNIT + 255) / 256;
-    static_assert(NA * 256 == 2 * 2 * BM * CH, "table tile must split evenly");
+    constexpr int NU = (NUNIT + NT - 1) / NT;
+    static_assert(NUNIT % 64 == 0, "direct operand units must fill whole waves");
+    static_assert(NA * NT == 2 * 2 * BM * CH, "table tile must split evenly");
     // INV operand chunks: 4 consecutive n (two kappa of each parity) of one
     // field, 32 bytes; the JC chunks of a field's stage are taken by JC
     // consecutive lanes, so four lanes share each 128-byte line and one load
     // instruction of a wave touches 16 lines (one line per lane when each
     // lane read a whole run of 16 n)
     constexpr int JC = BK / 2;
-    constexpr int NIU = (BN / 2) * JC / 256;
-    static_assert(!INVERSE || (NIU * 256 == (BN / 2) * JC && 4 * NIU <= 16 * NU),
+    constexpr int NIU = (BN / 2) * JC / NT;
+    static_assert(!INVERSE || (NIU * NT == (BN / 2) * JC && 4 * NIU <= 16 * NU),
                   "inverse operand chunks must split evenly");
     // operand tiles As[p][h][i][kappa], Bs[p][h][j][kappa]; the direct form
     // reuses the same LDS to stage its output tile
@@ -515,7 +519,7 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
     const MBlock b = a.mb[m];
     const int row0 = it.tr * BM, col0 = it.tc * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
+    const int wr = (wave / NWN) * WM, wc = (wave % NWN) * WN;
     const int ncol = 2 * a.nfld;
     const int64_t sb = spec_base(a.trunc, m);
     // A operand rows are contiguous in kappa: inverse reads [p][r][k], direct [p][k][r]
@@ -533,7 +537,7 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
     float usc[NU];  // data scale 2^E_f (half form)
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-        const int idx = tid + u * 256;
+        const int idx = tid + u * NT;
         ufl[u] = INVERSE ? idx / CH : idx % (BN / 2);
         uon[u] = idx < NUNIT;
         usc[u] = 1.f;
@@ -549,7 +553,7 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
     for (int u = 0; u < NIU; ++u) {
         isc[u] = 1.f;
         if constexpr (F16 && INVERSE) {
-            const int f = col0 / 2 + (u * 256 + tid) / JC;
+            const int f = col0 / 2 + (u * NT + tid) / JC;
             if (f < a.nfld) isc[u] = ldexpf(1.f, field_exp(a.fmax, f, a.dbound));
         }
     }
@@ -564,7 +568,7 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
     auto meta = [&](int kk, RingPair (*mp)[NMQ], float (*mq)[NMQ]) __attribute__((always_inline)) {
 #pragma unroll
         for (int u = 0; u < NMU; ++u) {
-            int rc = (tid + u * 256) / (BN / 2);
+            int rc = (tid + u * NT) / (BN / 2);
             // with 64 fields per tile a unit's rings are uniform over a wave:
             // scalar loads into scalar registers
             if constexpr (BN / 2 == 64) rc = __builtin_amdgcn_readfirstlane(rc);
@@ -573,7 +577,8 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
                 int r = kk + rc * 8 + q;
                 RingPair o = {-1, -1};
                 float w = 0.f;
-                if ((BN / 2 == 64 || uon[u]) && r < b.R) {
+                // units are whole waves (NUNIT is a multiple of 64), so uon is wave-uniform
+                if ((NUNIT % NT == 0 || __builtin_amdgcn_readfirstlane(uon[u] ? 1 : 0)) && r < b.R) {
                     o = a.ring_pair[b.j0 + r];
                     w = a.adjoint ? 1.f : ((const float *)a.ring_q)[b.j0 + r];
                 }
@@ -586,7 +591,7 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
     auto load = [&](int kk) __attribute__((always_inline)) {
 #pragma unroll
         for (int v = 0; v < NA; ++v) {
-            int idx = tid + v * 256;
+            int idx = tid + v * NT;
             int p = idx / (2 * BM * CH), rem = idx - p * 2 * BM * CH;
             int hl = rem / (BM * CH);
             rem -= hl * BM * CH;
@@ -598,7 +603,7 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
         if constexpr (INVERSE) {
 #pragma unroll
             for (int u = 0; u < NIU; ++u) {
-                const int f = col0 / 2 + (u * 256 + tid) / JC;
+                const int f = col0 / 2 + (u * NT + tid) / JC;
                 const int nrel = 2 * kk + 4 * ij;
                 const float2 *src = (const float2 *)a.in + (int64_t)f * a.nspec + sb + nrel;
                 if (f < a.nfld && m + nrel + 3 <= a.trunc) {
@@ -637,7 +642,7 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
     auto store = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int v = 0; v < NA; ++v) {
-            int idx = tid + v * 256;
+            int idx = tid + v * NT;
             int p = idx / (2 * BM * CH), rem = idx - p * 2 * BM * CH;
             int hl = rem / (BM * CH);
             rem -= hl * BM * CH;
@@ -648,7 +653,7 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
             // chunk u holds n = 4 ij + t (t = 0..3): kappa 2 ij + t / 2 of parity t & 1
 #pragma unroll
             for (int u = 0; u < NIU; ++u) {
-                const int fl = (u * 256 + tid) / JC;
+                const int fl = (u * NT + tid) / JC;
                 const float sc = isc[u];
                 unsigned hi, lo;
 #pragma unroll
@@ -668,7 +673,7 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
                 if (!uon[u]) continue;
-                const int idx = tid + u * 256;
+                const int idx = tid + u * NT;
                 const float sc = usc[u];
                 float x[8];
                 u32x4 hi, lo;
@@ -814,7 +819,8 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             __syncthreads();
-            if ((wave & 1) == h) {
+            // the waves whose columns fall in this half
+            if ((wave % NWN) / (NWN / 2) == h) {
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -824,7 +830,7 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
                                 const int k = wr + i * 16 + 4 * (lane >> 4) + v;
-                                const int cl = j * 16 + (lane & 15);
+                                const int cl = wc - h * (BN / 2) + j * 16 + (lane & 15);
                                 float val = ldexpf(acc[p][i][j][v], -eu[j]);
                                 if (m == 0 && (cl & 1)) val = 0.f;
                                 st[((cl >> 1) * RS + p + 2 * k) * 2 + (cl & 1)] = val;
@@ -832,7 +838,7 @@ __global__ __launch_bounds__(256) void k_leg_split(GemmArgs a)
             }
             __syncthreads();
             const int fbase = col0 / 2 + h * FH;
-            for (int fl = wave; fl < FH; fl += 4) {
+            for (int fl = wave; fl < FH; fl += NW) {
                 const int f = fbase + fl;
                 if (f >= a.nfld) break;
                 float2 *dst = spec + (int64_t)f * a.nspec + sb + nrel0;
@@ -982,9 +988,9 @@ hipError_t launch_split(const Plan &p, const GemmArgs &a, int bm, int bn, hipStr
     const int grid = (int)items.size();
     if (!p.shapes_ok || grid < 1) return hipErrorInvalidValue;
     if (bm == 128 && bn == 128)
-        k_leg_split<F16, 128, 128, 32, INV><<<grid, 256, 0, s>>>(a);
+        k_leg_split<F16, 128, 128, 32, INV, 8><<<grid, 512, 0, s>>>(a);
     else if (bm == 64 && bn == 128)
-        k_leg_split<F16, 64, 128, 32, INV><<<grid, 256, 0, s>>>(a);
+        k_leg_split<F16, 64, 128, 32, INV, 4><<<grid, 256, 0, s>>>(a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -992,7 +998,8 @@ hipError_t launch_split(const Plan &p, const GemmArgs &a, int bm, int bn, hipStr
 
 }  // namespace
 
-// Tile shapes with a kernel instantiation, the default first.
+// Tile shapes with a kernel instantiation (split forms: 128 x 128 with eight
+// waves, 64 x 128 with four).
 int gemm_tile_candidates(int prec, int *bm, int *bn, int max)
 {
     static const int f32[][2] = {{128, 128}, {64, 128}, {128, 64}};
