@@ -86,8 +86,8 @@ struct GemmArgs {
 __device__ inline int64_t spec_base(int trunc, int m) { return (int64_t)m * (2 * trunc + 3 - m) / 2; }
 
 // ---------------------------------------------------------------------------
-// FP64 / FP32.  256 threads as 2 x 2 waves, each owning a (BM/2) x (BN/2)
-// tile per parity.  LDS tiles are K-major (As[buf][p][kappa][i],
+// FP64 / FP32.  NW (4 or 8) waves as 2 x (NW/2), each owning a (BM/2) x
+// (2 BN/NW) tile per parity.  LDS tiles are K-major (As[buf][p][kappa][i],
 // Bs[buf][p][kappa][j]) and double-buffered: the global loads of stage s+1
 // are issued into registers before the MFMAs of stage s and written to the
 // other buffer after them, with one barrier per stage.
