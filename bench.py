@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-pair", action="store_true", help="skip the inverse + adjoint-of-inverse pair")
     ap.add_argument("--no-energy", action="store_true", help="skip the amd-smi energy window")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-peaks", action="store_true",
+                    help="skip the peak probes (matrix-core and vector-ALU loops, HBM copy and read)")
     ap.add_argument("--no-single-core", action="store_true",
                     help="skip the one-thread oracle run of one field")
     ap.add_argument("--cpu-fields", type=int, default=0,
@@ -341,6 +343,29 @@ def form_summary(res, prec, wl):
             "fft_hbm_frac": {k: rf[k]["frac"] for k in rf if k.startswith("ring")}}
 
 
+# the probe whose measured rate stands beside each form's published MFMA peak
+PEAK_PROBE = {"fp64": "mfma_f64_TF", "fp32": "mfma_f32_TF", "bf16x3": "mfma_bf16_TF", "fp16x3": "mfma_f16_TF"}
+
+
+def measure_peaks(torch, shtx):
+    """Rates this GPU sustains (shtx_probe_peak): matrix-core loops per
+    precision, the non-packed FP32 vector-ALU rate, and a 1 GiB HBM copy and
+    read; the published peaks stay the roofline denominators."""
+    out = {}
+    for kind in ("mfma_f64", "mfma_f32", "mfma_bf16", "mfma_f16", "valu_f32"):
+        out[kind + "_TF"] = shtx.probe_peak(kind)
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+    dst = torch.empty_like(src)
+    out["hbm_copy_GB_s"] = shtx.probe_peak("hbm_copy", src, dst)
+    out["hbm_read_GB_s"] = shtx.probe_peak("hbm_read", src)
+    del src, dst
+    torch.cuda.empty_cache()
+    out["method"] = ("one warm-up and three timed launches each (HIP events): 8 independent MFMA chains per wave "
+                     "on register operands; 8 FP32 FMA chains per lane; 16-byte grid-stride copy (read + write "
+                     "counted) and read of 1 GiB")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -439,6 +464,14 @@ def main():
         line["forms"] = forms
         if "fp64" in forms:
             line["vs_fp64_plain_same_gpu"] = line["value"] / forms["fp64"]["fields_per_s"]
+    if not args.no_peaks:
+        say("peak probes")
+        peaks = measure_peaks(torch, shtx)
+        line["peaks_measured"] = peaks
+        key = {"TFLOP/s": PEAK_PROBE[args.prec], "GB/s": "hbm_copy_GB_s"}[roofline["unit"]]
+        if peaks.get(key):
+            line["roofline_vs_measured"] = {"peak": peaks[key], "probe": key,
+                                            "frac": roofline["achieved"] / peaks[key]}
     print(json.dumps(line), flush=True)
 
 

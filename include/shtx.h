@@ -226,6 +226,37 @@ int shtx_timing_read(shtx_plan p, double *ms_sum, int32_t *count);
 
 int shtx_plan_destroy(shtx_plan p);
 
+/* Peak probes (measurement only; no plan, no transform).  The roofline
+ * fractions are set against the vendor peaks of MI355X; these probes measure
+ * what this GPU sustains for the same units, as the measurement recipe asks
+ * (a matrix-core loop and a copy kernel; the paper's roofline takes its
+ * memory bandwidth from the STREAM benchmark, Section 4.1.2).
+ *   SHTX_PROBE_MFMA_F64/F32  register-resident loop of 8 independent
+ *                            16x16x4 MFMA chains per wave on every CU;
+ *   SHTX_PROBE_MFMA_BF16/F16 the same with 16x16x32 MFMAs;
+ *   SHTX_PROBE_VALU_F32      8 independent FP32 FMA chains per lane (packed
+ *                            FP32 instructions are not used by this library);
+ *   SHTX_PROBE_HBM_COPY      copies `bytes` from src_d to dst_d, 16 bytes per
+ *                            lane, grid-stride (bytes read + bytes written);
+ *   SHTX_PROBE_HBM_READ      reads `bytes` from src_d.
+ * One warm-up launch, then three launches timed with HIP events on
+ * hip_stream (the call synchronises on them).  *rate receives TFLOP/s
+ * (compute kinds) or GB/s (memory kinds).  dst_d: device memory, 16-byte
+ * aligned, at least 16 bytes for the compute kinds and the read probe (never
+ * written at run time), `bytes` for the copy; src_d: device memory, 16-byte
+ * aligned, for the memory kinds.  bytes: a multiple of 16, at least 1 MiB,
+ * for the memory kinds (ignored otherwise).  Overlapping copy buffers, host
+ * pointers, a NULL rate or an unknown kind give SHTX_EINVAL; a failed HIP
+ * call SHTX_EHIP.  The probes take a few tens of milliseconds each. */
+#define SHTX_PROBE_MFMA_F64 0
+#define SHTX_PROBE_MFMA_F32 1
+#define SHTX_PROBE_MFMA_BF16 2
+#define SHTX_PROBE_MFMA_F16 3
+#define SHTX_PROBE_VALU_F32 4
+#define SHTX_PROBE_HBM_COPY 5
+#define SHTX_PROBE_HBM_READ 6
+int shtx_probe_peak(int kind, const void *src_d, void *dst_d, size_t bytes, double *rate, void *hip_stream);
+
 const char *shtx_strerror(int code);
 
 #ifdef __cplusplus

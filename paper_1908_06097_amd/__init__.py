@@ -26,13 +26,16 @@ FLAG_GRAPH = 1
 FLAG_TIMING = 2
 FLAG_AUTOTUNE = 4
 FLAG_UV = 8
+# shtx_probe_peak kinds: compute probes return TFLOP/s, memory probes GB/s
+PROBES = {"mfma_f64": 0, "mfma_f32": 1, "mfma_bf16": 2, "mfma_f16": 3, "valu_f32": 4, "hbm_copy": 5,
+          "hbm_read": 6}
 
 _lib = None
 
 _EXPORTS = ("shtx_plan_create", "shtx_plan_check", "shtx_plan_check_shapes", "shtx_plan_set_shapes", "shtx_plan_info", "shtx_plan_ring_lengths", "shtx_plan_nodes",
             "shtx_plan_legendre", "shtx_inv_trans", "shtx_dir_trans", "shtx_inv_trans_adj",
             "shtx_dir_trans_adj", "shtx_uv_trans", "shtx_inv_trans_noalloc", "shtx_timing_reset", "shtx_timing_enable", "shtx_timing_read", "shtx_plan_destroy",
-            "shtx_strerror")
+            "shtx_probe_peak", "shtx_strerror")
 
 
 class ShtxError(RuntimeError):
@@ -74,6 +77,7 @@ def load_library():
     lib.shtx_timing_enable.argtypes = [vp, i32]
     lib.shtx_timing_read.argtypes = [vp, ctypes.c_void_p, ctypes.c_void_p]
     lib.shtx_plan_destroy.argtypes = [vp]
+    lib.shtx_probe_peak.argtypes = [i32, vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), vp]
     lib.shtx_strerror.argtypes = [i32]
     lib.shtx_strerror.restype = ctypes.c_char_p
     for name in _EXPORTS:
@@ -81,6 +85,35 @@ def load_library():
             getattr(lib, name).restype = i32
     _lib = lib
     return lib
+
+
+def probe_peak(kind, src=None, dst=None):
+    """Rate one peak probe measures on torch's current device and stream
+    (shtx_probe_peak): TFLOP/s for "mfma_f64", "mfma_f32", "mfma_bf16",
+    "mfma_f16", "valu_f32"; GB/s for "hbm_copy" (src -> dst, both counted)
+    and "hbm_read" (src).  src/dst: contiguous device tensors of the same
+    byte size (a multiple of 16, at least 1 MiB) for the memory probes."""
+    import torch
+    if kind not in PROBES:
+        raise ShtxError(f"unknown probe {kind!r}; expected one of {sorted(PROBES)}")
+    if not torch.cuda.is_available():
+        raise ShtxError("libshtx needs a ROCm GPU; no CPU fallback exists")
+    nbytes = 0
+    if kind in ("hbm_copy", "hbm_read"):
+        if src is None or not src.is_cuda or not src.is_contiguous():
+            raise ShtxError("memory probes need a contiguous device tensor src")
+        nbytes = src.numel() * src.element_size()
+        if kind == "hbm_copy" and (dst is None or not dst.is_cuda or not dst.is_contiguous()
+                                   or dst.numel() * dst.element_size() < nbytes):
+            raise ShtxError("the copy probe needs a contiguous device tensor dst at least as large as src")
+    if dst is None:
+        dst = torch.empty(4, dtype=torch.float32, device=src.device if src is not None else "cuda")
+    rate = ctypes.c_double(0.0)
+    stream = torch.cuda.current_stream(dst.device).cuda_stream
+    _check(load_library().shtx_probe_peak(PROBES[kind], ctypes.c_void_p(src.data_ptr() if src is not None else 0),
+                                          ctypes.c_void_p(dst.data_ptr()), ctypes.c_size_t(nbytes),
+                                          ctypes.byref(rate), ctypes.c_void_p(stream)), "shtx_probe_peak")
+    return rate.value
 
 
 def plan_check(trunc, grid="octahedral", nlat=None, nfld=1, prec="fp32", nlon_full=0):

@@ -13,12 +13,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libshtx.so")
-SOURCES = ["plan.cpp", "capi.cpp", "autotune.cpp", "k_tables.hip", "k_gemm.hip", "k_fft.hip", "k_wind.hip"]
+SOURCES = ["plan.cpp", "capi.cpp", "autotune.cpp", "k_tables.hip", "k_gemm.hip", "k_fft.hip", "k_wind.hip",
+           "k_probe.hip"]
 BUILD = os.path.join(HERE, "_build")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-I", INCLUDE,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]
+# The peak probes' MFMA loops keep their accumulators in vector registers
+# (with the accumulation-register form the compiler copies every accumulator
+# out and back around each iteration's MFMAs).
+EXTRA_FLAGS = {"k_probe.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def build_id():
@@ -33,7 +38,8 @@ def build_id():
 def _compile(src, verbose, bid):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"]
-    cmd = ["hipcc", *lang, *FLAGS, f'-DSHTX_BUILD_ID="{bid}"', "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = ["hipcc", *lang, *FLAGS, *EXTRA_FLAGS.get(src, []), f'-DSHTX_BUILD_ID="{bid}"', "-c",
+           os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

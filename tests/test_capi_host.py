@@ -34,6 +34,15 @@ def test_exports_every_declared_symbol(lib):
         assert hasattr(lib, n), n
 
 
+def test_probe_peak_rejects_bad_arguments_before_any_launch(lib):
+    import ctypes
+    rate = ctypes.c_double(1.0)
+    # unknown kinds and a missing result pointer are refused on the host
+    assert lib.shtx_probe_peak(-1, None, None, 0, ctypes.byref(rate), None) == -1
+    assert lib.shtx_probe_peak(7, None, None, 0, ctypes.byref(rate), None) == -1
+    assert lib.shtx_probe_peak(1, None, None, 0, None, None) == -1
+
+
 def test_strerror(lib):
     assert lib.shtx_strerror(0) == b"success"
     assert lib.shtx_strerror(-1) == b"invalid argument"
