@@ -24,7 +24,7 @@ def _spec(torch, plan, key=21, fields=None):
     return torch.from_numpy(si.spectral_fields(plan.trunc, key, fields)).to(plan.complex_dtype).cuda()
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3", "fp64"])
 def test_graph_replay_matches_eager(prec):
     torch, shtx = _env()
     eager = shtx.Plan(63, "octahedral", 128, 5, prec)
@@ -112,14 +112,45 @@ def test_fields_are_independent(prec):
     assert torch.equal(plan.dir(g)[0], plan.dir(h)[0])
 
 
-def test_nan_propagates_only_within_its_field():
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+def test_nan_propagates_only_within_its_field(prec):
+    """A NaN stays in its field in both directions (the split-half form's
+    per-field scales are taken from a maximum that ignores or isolates it)."""
     torch, shtx = _env()
-    plan = shtx.Plan(63, "octahedral", 128, 3, "fp32")
+    plan = shtx.Plan(63, "octahedral", 128, 3, prec)
     a = _spec(torch, plan)
     a[1, 10] = float("nan")
     g = plan.inv(a)
     assert torch.isnan(g[1]).any()
     assert not torch.isnan(g[0]).any() and not torch.isnan(g[2]).any()
+    g = plan.inv(_spec(torch, plan))
+    g[2, 100] = float("nan")
+    b = plan.dir(g)
+    assert torch.isnan(torch.view_as_real(b[2])).any()
+    assert not torch.isnan(torch.view_as_real(b[:2])).any()
+
+
+# reduced-precision forms on the degenerate shapes: max relative error bounds
+# (split IEEE half reaches FP32's accuracy)
+DEGENERATE_TOL = {"fp32": 1e-5, "bf16x3": 1e-4, "fp16x3": 1e-5}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
+@pytest.mark.parametrize("trunc,grid,nlat,nlon", [(0, "octahedral", 2, 0), (1, "octahedral", 4, 0),
+                                                   (2, "full", 4, 6), (7, "full", 8, 16)])
+def test_degenerate_sizes_reduced_precision(trunc, grid, nlat, nlon, prec):
+    import oracle
+    torch, shtx = _env()
+    plan = shtx.Plan(trunc, grid, nlat, 3, prec, nlon_full=nlon)
+    nl = plan.ring_lengths()
+    a = si.spectral_fields(trunc, 32, [0, 1, 2])
+    g = plan.inv(torch.from_numpy(a).to(torch.complex64).cuda()).double().cpu().numpy()
+    ref = oracle.inv(trunc, nl, a)
+    tol = DEGENERATE_TOL[prec]
+    assert np.max(np.abs(g - ref)) <= tol * np.max(np.abs(ref)), np.max(np.abs(g - ref)) / np.max(np.abs(ref))
+    b = plan.dir(torch.from_numpy(ref).float().cuda()).cpu().numpy().astype(np.complex128)
+    bref = oracle.dir(trunc, nl, ref)
+    assert np.max(np.abs(b - bref)) <= tol * np.max(np.abs(bref)), np.max(np.abs(b - bref)) / np.max(np.abs(bref))
 
 
 @pytest.mark.parametrize("trunc,grid,nlat,nlon", [(0, "octahedral", 2, 0), (1, "octahedral", 4, 0),
