@@ -84,7 +84,9 @@ enum shtx_status {
 #define SHTX_FLAG_GRAPH 1u /* replay each transform as a captured hipGraph */
 /* Tile autotuning: plan creation times every candidate tile shape of the
  * two Legendre GEMM launches and every candidate ring-FFT blocking on the
- * plan's own shape (zero-filled scratch inputs) and keeps the fastest; the
+ * plan's own shape (scratch operands filled with a pseudo-random integer hash
+ * of the index: constant operands change the matrix cores' power draw and
+ * clock) and keeps the fastest; the
  * choice is reported in shtx_info.  If the environment variable
  * SHTX_TUNE_CACHE names a file, choices are looked up there first and
  * appended after timing, one JSON object per line, keyed by GPU
