@@ -48,6 +48,66 @@ def test_graph_replay_matches_eager(prec):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16x3"])
+def test_caller_graph_capture(prec):
+    """A caller's own graph (torch.cuda.graph) captures a plan's transforms:
+    every replay, with eager work on the same buffers between replays,
+    equals the eager result bit for bit (the split-half form's per-field
+    maxima are cleared by a kernel, so each replay starts from zero)."""
+    torch, shtx = _env()
+    plan = shtx.Plan(63, "octahedral", 128, 5, prec)
+    a = _spec(torch, plan)
+    ref_g = plan.inv(a)
+    ref_s = plan.dir(ref_g)
+    g = torch.empty_like(ref_g)
+    s = torch.empty_like(ref_s)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up outside the capture
+        plan.inv(a, out=g)
+        plan.dir(g, out=s)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.inv(a, out=g)
+        plan.dir(g, out=s)
+    for rep in range(4):
+        g.fill_(float("nan"))
+        s.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(g, ref_g), rep
+        assert torch.equal(s, ref_s), rep
+    del graph
+    torch.cuda.synchronize()
+
+
+def test_two_plans_on_two_streams():
+    """Two plans used at the same time from two streams give the results each
+    gives alone (no state is shared between plans)."""
+    torch, shtx = _env()
+    pa = shtx.Plan(127, "octahedral", 256, 7, "fp32")
+    pb = shtx.Plan(127, "octahedral", 256, 11, "fp16x3")
+    a, b = _spec(torch, pa, key=41), _spec(torch, pb, key=42)
+    ref_a = pa.dir(pa.inv(a))
+    ref_b = pb.dir(pb.inv(b))
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    s1.wait_stream(torch.cuda.current_stream())
+    s2.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            ra = pa.dir(pa.inv(a))
+        with torch.cuda.stream(s2):
+            rb = pb.dir(pb.inv(b))
+        outs.append((ra, rb))
+    torch.cuda.synchronize()
+    for ra, rb in outs:
+        assert torch.equal(ra, ref_a) and torch.equal(rb, ref_b)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
 def test_graph_path_matches_oracle(prec):
     """The hipGraph replay path (the one the benchmark times) against the
