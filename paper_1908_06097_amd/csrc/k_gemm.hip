@@ -957,16 +957,29 @@ hipError_t launch_mfma(const Plan &p, const GemmArgs &a, int bm, int bn, hipStre
 }
 
 // Largest magnitude of each field's spectral coefficients (Re and Im of
-// every a_n^m except Im a_n^0, which the transforms ignore), as float bits,
-// one block per field: the bound from which the half form scales the
-// inverse-shaped GEMM's data operand.
+// every a_n^m except Im a_n^0, which the transforms ignore), as float bits:
+// the bound from which the half form scales the inverse-shaped GEMM's data
+// operand.  Blocks (chunk, field) each take a contiguous chunk of one
+// field's coefficients and fold their maximum into fmax[f] with an atomic
+// max (non-negative floats order as their bits), after k_clear_u32 has
+// zeroed it; the maximum does not depend on the order.
+constexpr int kAbsmaxChunks = 8;
+
+__global__ void k_clear_u32(unsigned *x, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0u;
+}
+
 __global__ __launch_bounds__(1024) void k_spec_absmax(const float2 *spec, int64_t nspec, int trunc, unsigned *fmax)
 {
     __shared__ float red[16];
-    const int f = blockIdx.x;
+    const int f = blockIdx.y;
+    const int64_t chunk = (nspec + kAbsmaxChunks - 1) / kAbsmaxChunks;
+    const int64_t i0 = blockIdx.x * chunk, i1 = min(nspec, i0 + chunk);
     const float2 *row = spec + (int64_t)f * nspec;
     float mx = 0.f;
-    for (int64_t i = threadIdx.x; i < nspec; i += 1024) {
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 1024) {
         const float2 z = row[i];
         mx = fmaxf(mx, fabsf(z.x));
         if (i > trunc) mx = fmaxf(mx, fabsf(z.y));  // index i <= N is m = 0
@@ -977,7 +990,7 @@ __global__ __launch_bounds__(1024) void k_spec_absmax(const float2 *spec, int64_
     if (threadIdx.x == 0) {
         float t = 0.f;
         for (int w = 0; w < 16; ++w) t = fmaxf(t, red[w]);
-        fmax[f] = __float_as_uint(t);
+        atomicMax(fmax + f, __float_as_uint(t));
     }
 }
 
@@ -1041,7 +1054,8 @@ hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, unsi
     if (p.prec == SHTX_FP32) return launch_mfma<float, 16, true>(p, a, p.inv_bm, p.inv_bn, s);
     if (p.prec == SHTX_FP16X3) {
         if (!fmax) return hipErrorInvalidValue;
-        k_spec_absmax<<<p.nfld, 1024, 0, s>>>((const float2 *)spec, p.nspec, p.trunc, fmax);
+        k_clear_u32<<<(p.nfld + 255) / 256, 256, 0, s>>>(fmax, p.nfld);
+        k_spec_absmax<<<dim3(kAbsmaxChunks, p.nfld), 1024, 0, s>>>((const float2 *)spec, p.nspec, p.trunc, fmax);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         return launch_split<true, true>(p, a, p.inv_bm, p.inv_bn, s);

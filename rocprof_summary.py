@@ -40,8 +40,9 @@ SQ_COUNTERS = ["SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ
 def classify(name):
     if "k_probe" in name:
         return None  # the bench's peak probes, not a transform stage
-    if "k_spec_absmax" in name:
-        # the split-half form's per-field maxima, launched with the inverse GEMM
+    if "k_spec_absmax" in name or "k_clear_u32" in name:
+        # the split-half form's per-field maxima (cleared, then taken), launched
+        # with the inverse GEMM
         return "legendre_inverse_gemm"
     if "k_uv_spec" in name:
         # the wind step, launched with the inverse GEMM it feeds
