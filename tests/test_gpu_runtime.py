@@ -264,8 +264,16 @@ def test_argument_errors():
     assert lib.shtx_plan_legendre(plan._h, 32, None) == -1
 
 
+def _library_loaded(shtx):
+    """Create and destroy one small plan, so that the library's code objects
+    (and its static scratch array) are resident before a memory baseline."""
+    shtx.Plan(15, "octahedral", 32, 1, "fp32").close()
+
+
 def test_plan_create_destroy_cycles():
     torch, shtx = _env()
+    _library_loaded(shtx)
+    torch.cuda.synchronize()
     free0, _ = torch.cuda.mem_get_info()
     for _ in range(5):
         p = shtx.Plan(255, "octahedral", 512, 16, "bf16x3")
@@ -273,3 +281,23 @@ def test_plan_create_destroy_cycles():
     torch.cuda.synchronize()
     free1, _ = torch.cuda.mem_get_info()
     assert free1 >= free0 - (64 << 20)
+
+
+def test_plan_beyond_device_memory_fails_cleanly():
+    """A plan whose Fourier workspace cannot fit in HBM (TCo1279, 8000 fields
+    in FP64: about 316 GB) fails with SHTX_ENOMEM, frees what it had
+    allocated (tables included) and leaves the device usable."""
+    torch, shtx = _env()
+    _library_loaded(shtx)
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    with pytest.raises(shtx.ShtxError) as err:
+        shtx.Plan(1279, "octahedral", 2560, 8000, "fp64")
+    assert "out of memory" in str(err.value), str(err.value)
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    assert free1 >= free0 - (64 << 20), (free0, free1)
+    plan = shtx.Plan(31, "octahedral", 64, 2, "fp64")
+    a = _spec(torch, plan)
+    assert torch.isfinite(torch.view_as_real(plan.dir(plan.inv(a)))).all()
+    plan.close()
