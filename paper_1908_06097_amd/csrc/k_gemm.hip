@@ -102,6 +102,66 @@ struct __attribute__((aligned(2 * sizeof(T)))) Vec2 {
     T x, y;
 };
 
+// Inverse epilogue through LDS (single precision and the split forms): the
+// tile's rows of one hemisphere at a time are staged as [row][column] floats
+// (16-column groups swizzled by row so that the fragment writes spread over
+// the banks) and written out as contiguous runs over the fields of each ring
+// row, 16 bytes per lane, instead of 4-byte stores scattered over 64-byte
+// pieces.  val(hs, i, j, v) is the fragment value of hemisphere hs (0 north,
+// 1 south).  Called by every thread of the block after the K loop's final
+// barrier; st must hold BM x BN floats.
+typedef float f32x4s __attribute__((ext_vector_type(4)));
+typedef float f32x4s8 __attribute__((ext_vector_type(4), aligned(8)));
+template <int BM, int BN, int NT, int FM, int FN, typename ValFn>
+__device__ inline void inv_epilogue_staged(const GemmArgs &a, const MBlock &b, int m, int row0, int col0, int wr,
+                                           int wc, int lane, int tid, float *st, ValFn val)
+{
+    constexpr int TPR = BN / 4, RPP = NT / TPR, NPASS = BM / RPP;
+    static_assert(BN >= 64 && NPASS * RPP == BM, "staged rows must split evenly over the block");
+    const int ncol = 2 * a.nfld;
+    // ring offsets of the rows this thread writes, fetched before the staging
+    RingPair ro[NPASS];
+#pragma unroll
+    for (int k = 0; k < NPASS; ++k) {
+        const int r = row0 + tid / TPR + k * RPP;
+        ro[k] = RingPair{-1, -1};
+        if (r < b.R) ro[k] = a.ring_pair[b.j0 + r];
+    }
+    float *four = (float *)a.out;
+    const int cq = 4 * (tid % TPR);
+#pragma unroll
+    for (int hs = 0; hs < 2; ++hs) {
+        if (hs) __syncthreads();  // the north half has been read out
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = wr + i * 16 + 4 * (lane >> 4) + v;
+                    const int c = wc + j * 16 + (lane & 15);
+                    st[r * BN + (c ^ ((r & 12) << 2))] = val(hs, i, j, v);
+                }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < NPASS; ++k) {
+            const RingPair o = ro[k];
+            const int rl = tid / TPR + k * RPP;
+            const int c = col0 + cq;
+            if (o.n < 0 || c >= ncol) continue;
+            const f32x4s x = *reinterpret_cast<const f32x4s *>(&st[rl * BN + (cq ^ ((rl & 12) << 2))]);
+            float *dst = four + 2 * ((int64_t)(hs ? o.s : o.n) + m) * a.nfld + c;
+            if (c + 3 < ncol) {
+                *reinterpret_cast<f32x4s8 *>(dst) = x;
+            } else {
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    if (c + t < ncol) dst[t] = x[t];
+            }
+        }
+    }
+}
+
 template <typename T, int BM, int BN, int BK, bool INV, int NW = 4>
 __global__ __launch_bounds__(64 * NW, 2) void k_leg_mfma(GemmArgs a)
 {
@@ -304,7 +364,14 @@ __global__ __launch_bounds__(64 * NW, 2) void k_leg_mfma(GemmArgs a)
         __syncthreads();
     }
 
-    if (INV) {
+    if constexpr (INV && sizeof(T) == 4) {
+        static_assert(BM * BN <= NSMEM, "staged inverse tile must fit the operand LDS");
+        inv_epilogue_staged<BM, BN, NT, FM, FN>(a, b, m, row0, col0, wr, wc, lane, tid, reinterpret_cast<float *>(smem),
+                                                [&](int hs, int i, int j, int v) {
+                                                    const float s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
+                                                    return hs ? s0 - s1 : s0 + s1;
+                                                });
+    } else if constexpr (INV) {
         T *four = (T *)a.out;
         // all rows' ring offsets first, so that their loads overlap
         RingPair ro[FM][4];
@@ -403,7 +470,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_leg_mfma(GemmArgs a)
 // of two bfloat16 or two IEEE-half values, and a tile product is three MFMAs
 // (hi*lo + lo*hi + hi*hi; lo*lo is dropped).  16x16x32 MFMA: lane l supplies
 // A[l%16][8(l/16)..+7] and B[8(l/16)..+7][l%16]; LDS tiles are row-major
-// with kappa contiguous: As[p][h][i][kappa], Bs[p][h][j][kappa] (h = hi, lo).
+// with kappa contiguous: As[p][h][i][kappa], Bs[p][h][j][kappa] (h = hi, lo),
+// unpadded, the 16-byte chunks of each row permuted by an XOR swizzle.
 //
 // The table is stored already split, scaled by 2^e_m per m.  The data
 // operand is split here, once per block and stage, with the packed
@@ -488,8 +556,21 @@ __global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
     constexpr int NT = 64 * NW, NWN = NW / 2;
     constexpr int WM = BM / 2, WN = BN / NWN, FM = WM / 16, FN = WN / 16;
     static_assert(NW == 4 || NW == 8, "4 or 8 waves per block");
-    constexpr int LDK = BK + 8;  // 16-byte aligned rows, staggered banks
-    constexpr int CH = BK / 8;   // 16-byte chunks per tile row
+    constexpr int LDK = BK;     // unpadded rows; 16-byte chunks swizzled per row
+    constexpr int CH = BK / 8;  // 16-byte chunks per tile row
+    static_assert(CH == 4 || CH == 8, "the chunk swizzle permutes four or eight chunks");
+    // physical chunk of logical chunk c in tile row r: c ^ sw(r).  Rows PR
+    // apart share banks (512 bytes); the bits of r / PR go to the swizzle's
+    // upper bits and bit 4 of r to bit 0, so that the MFMA reads (16 rows, two
+    // chunks per 32 lanes) and the direct operand stores (32 rows, one chunk)
+    // meet every bank once
+    constexpr int PR = 32 / CH;
+    auto sw = [](int r) __attribute__((always_inline)) { return (((r / PR) & (CH / 2 - 1)) << 1) | ((r >> 4) & 1); };
+    // LDS row of operand column (field fl, re/im ri): the inverse keeps them
+    // interleaved, the direct places all real parts before all imaginary ones
+    auto brow = [](int fl, int ri) __attribute__((always_inline)) {
+        return INVERSE ? 2 * fl + ri : ri * (BN / 2) + fl;
+    };
     constexpr int NA = (2 * 2 * BM * CH) / NT;  // table chunk loads per thread
     // DIR operand units: (field, 8 consecutive rings, north and south)
     constexpr int NUNIT = (BN / 2) * CH;
@@ -507,7 +588,11 @@ __global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
                   "inverse operand chunks must split evenly");
     // operand tiles As[p][h][i][kappa], Bs[p][h][j][kappa]; the direct form
     // reuses the same LDS to stage its output tile
-    constexpr int NSMEM16 = 2 * 2 * (BM + BN) * LDK;
+    constexpr int NOPER16 = 2 * 2 * (BM + BN) * LDK;
+    // the direct form stages one half of its output columns (BN / 4 fields of
+    // 2 BM + 1 complex values) in the same LDS
+    constexpr int NSTAGE16 = INVERSE ? 0 : (BN / 4) * (2 * BM + 1) * 2 * 2;
+    constexpr int NSMEM16 = NOPER16 > NSTAGE16 ? NOPER16 : NSTAGE16;
     __shared__ __attribute__((aligned(16))) unsigned short smem16[NSMEM16];
     auto As = reinterpret_cast<unsigned short(*)[2][BM][LDK]>(smem16);
     auto Bs = reinterpret_cast<unsigned short(*)[2][BN][LDK]>(smem16 + 2 * 2 * BM * LDK);
@@ -647,7 +732,7 @@ __global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
             int hl = rem / (BM * CH);
             rem -= hl * BM * CH;
             int i = rem / CH, ch = rem - i * CH;
-            *reinterpret_cast<u32x4 *>(&As[p][hl][i][ch * 8]) = ra[v];
+            *reinterpret_cast<u32x4 *>(&As[p][hl][i][(ch ^ sw(i)) * 8]) = ra[v];
         }
         if constexpr (INVERSE) {
             // chunk u holds n = 4 ij + t (t = 0..3): kappa 2 ij + t / 2 of parity t & 1
@@ -656,17 +741,19 @@ __global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
                 const int fl = (u * NT + tid) / JC;
                 const float sc = isc[u];
                 unsigned hi, lo;
+                const int r0 = brow(fl, 0), r1 = brow(fl, 1);
+                const int k0 = ((ij >> 2) ^ sw(r0)) * 8 + 2 * (ij & 3), k1 = ((ij >> 2) ^ sw(r1)) * 8 + 2 * (ij & 3);
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
                     split2<F16>(rv[0][4 * u + p].x * sc, rv[0][4 * u + 2 + p].x * sc, hi, lo);
-                    *reinterpret_cast<unsigned *>(&Bs[p][0][2 * fl][2 * ij]) = hi;
-                    *reinterpret_cast<unsigned *>(&Bs[p][1][2 * fl][2 * ij]) = lo;
+                    *reinterpret_cast<unsigned *>(&Bs[p][0][r0][k0]) = hi;
+                    *reinterpret_cast<unsigned *>(&Bs[p][1][r0][k0]) = lo;
                     // Im a^0_n is ignored
                     const float y0 = m == 0 ? 0.f : rv[0][4 * u + p].y * sc;
                     const float y1 = m == 0 ? 0.f : rv[0][4 * u + 2 + p].y * sc;
                     split2<F16>(y0, y1, hi, lo);
-                    *reinterpret_cast<unsigned *>(&Bs[p][0][2 * fl + 1][2 * ij]) = hi;
-                    *reinterpret_cast<unsigned *>(&Bs[p][1][2 * fl + 1][2 * ij]) = lo;
+                    *reinterpret_cast<unsigned *>(&Bs[p][0][r1][k1]) = hi;
+                    *reinterpret_cast<unsigned *>(&Bs[p][1][r1][k1]) = lo;
                 }
             }
         } else {
@@ -679,19 +766,21 @@ __global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
                 u32x4 hi, lo;
                 // hemispheric fold: parity 0 takes q (north + south), parity 1 q (north - south)
                 const int cp = ufl[u], rc = idx / (BN / 2);
+                const int r0 = brow(cp, 0), r1 = brow(cp, 1);
+                const int k0 = (rc ^ sw(r0)) * 8, k1 = (rc ^ sw(r1)) * 8;
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
                     const float sg = p ? -1.f : 1.f;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) x[q] = (mq1[u][q] * sc) * (rv[u][2 * q].x + sg * rv[u][2 * q + 1].x);
                     split8<F16>(x, hi, lo);
-                    *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * cp][rc * 8]) = hi;
-                    *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * cp][rc * 8]) = lo;
+                    *reinterpret_cast<u32x4 *>(&Bs[p][0][r0][k0]) = hi;
+                    *reinterpret_cast<u32x4 *>(&Bs[p][1][r0][k0]) = lo;
 #pragma unroll
                     for (int q = 0; q < 8; ++q) x[q] = (mq1[u][q] * sc) * (rv[u][2 * q].y + sg * rv[u][2 * q + 1].y);
                     split8<F16>(x, hi, lo);
-                    *reinterpret_cast<u32x4 *>(&Bs[p][0][2 * cp + 1][rc * 8]) = hi;
-                    *reinterpret_cast<u32x4 *>(&Bs[p][1][2 * cp + 1][rc * 8]) = lo;
+                    *reinterpret_cast<u32x4 *>(&Bs[p][0][r1][k1]) = hi;
+                    *reinterpret_cast<u32x4 *>(&Bs[p][1][r1][k1]) = lo;
                 }
             }
         }
@@ -709,7 +798,9 @@ __global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
     // ragged edge of an m block or of the field range) still loads and
     // stores its share of the operand tiles but skips the MFMAs
     const bool mfma_on = __builtin_amdgcn_readfirstlane(
-        (row0 + wr < (INVERSE ? b.R : b.K0) && col0 + wc < ncol) ? 1 : 0);
+        (row0 + wr < (INVERSE ? b.R : b.K0) && (INVERSE ? col0 + wc < ncol : col0 / 2 + (wc & (BN / 2 - 1)) < a.nfld))
+            ? 1
+            : 0);
 
     // The K loop, in two copies: with MFMAs, and without them for a wave
     // whose sub-tile is wholly ragged (a wave-uniform branch outside the
@@ -735,21 +826,23 @@ __global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
             if constexpr (decltype(with_mfma)::value) {
 #pragma unroll
                 for (int q = 0; q < BK; q += 32) {
-                    const int kq = q + 8 * (lane >> 4);
+                    const int kc = q / 8 + (lane >> 4);
 #pragma unroll
                     for (int p = 0; p < 2; ++p) {
                         u32x4 ah[FM], al[FM], bh[FN], bl[FN];
 #pragma unroll
                         for (int i = 0; i < FM; ++i) {
                             const int ai = wr + i * 16 + (lane & 15);
-                            ah[i] = *reinterpret_cast<const u32x4 *>(&As[p][0][ai][kq]);
-                            al[i] = *reinterpret_cast<const u32x4 *>(&As[p][1][ai][kq]);
+                            const int ka = (kc ^ sw(ai)) * 8;
+                            ah[i] = *reinterpret_cast<const u32x4 *>(&As[p][0][ai][ka]);
+                            al[i] = *reinterpret_cast<const u32x4 *>(&As[p][1][ai][ka]);
                         }
 #pragma unroll
                         for (int j = 0; j < FN; ++j) {
                             const int bj = wc + j * 16 + (lane & 15);
-                            bh[j] = *reinterpret_cast<const u32x4 *>(&Bs[p][0][bj][kq]);
-                            bl[j] = *reinterpret_cast<const u32x4 *>(&Bs[p][1][bj][kq]);
+                            const int kb = (kc ^ sw(bj)) * 8;
+                            bh[j] = *reinterpret_cast<const u32x4 *>(&Bs[p][0][bj][kb]);
+                            bl[j] = *reinterpret_cast<const u32x4 *>(&Bs[p][1][bj][kb]);
                         }
 #pragma unroll
                         for (int i = 0; i < FM; ++i)
@@ -778,35 +871,18 @@ __global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
     for (int j = 0; j < FN; ++j) {
         eu[j] = b.e;
         if constexpr (F16) {
-            const int c = col0 + wc + j * 16 + (lane & 15);
-            if (c < ncol) eu[j] += field_exp(a.fmax, c >> 1, a.dbound);
+            const int bj = wc + j * 16 + (lane & 15);
+            const int f = INVERSE ? (col0 + bj) >> 1 : col0 / 2 + (bj & (BN / 2 - 1));
+            if (f < a.nfld) eu[j] += field_exp(a.fmax, f, a.dbound);
         }
     }
-    if (INVERSE) {
-        float *four = (float *)a.out;
-        RingPair ro[FM][4];
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int r = row0 + wr + i * 16 + 4 * (lane >> 4) + v;
-                ro[i][v] = RingPair{-1, -1};
-                if (r < b.R) ro[i][v] = a.ring_pair[b.j0 + r];
-            }
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const RingPair o = ro[i][v];
-                    int c = col0 + wc + j * 16 + (lane & 15);
-                    if (o.n >= 0 && c < ncol) {
-                        float s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
-                        four[2 * ((int64_t)o.n + m) * a.nfld + c] = ldexpf(s0 + s1, -eu[j]);
-                        four[2 * ((int64_t)o.s + m) * a.nfld + c] = ldexpf(s0 - s1, -eu[j]);
-                    }
-                }
+    if constexpr (INVERSE) {
+        static_assert(BM * BN * 2 <= NSMEM16, "staged inverse tile must fit the operand LDS");
+        inv_epilogue_staged<BM, BN, NT, FM, FN>(a, b, m, row0, col0, wr, wc, lane, tid, reinterpret_cast<float *>(smem16),
+                                                [&](int hs, int i, int j, int v) {
+                                                    const float s0 = acc[0][i][j][v], s1 = acc[1][i][j][v];
+                                                    return ldexpf(hs ? s0 - s1 : s0 + s1, -eu[j]);
+                                                });
     } else {
         // staged per column half as [field][n], written as contiguous runs
         // (as in k_leg_mfma)
@@ -820,21 +896,25 @@ __global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
         for (int h = 0; h < 2; ++h) {
             __syncthreads();
             // the waves whose columns fall in this half
-            if ((wave % NWN) / (NWN / 2) == h) {
+            // operand column bj is field bj % (BN / 2), real part for
+            // bj < BN / 2; fragments of 16 columns never straddle a half
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int bj0 = wc + j * 16;
+                if (((bj0 & (BN / 2 - 1)) / FH) != h) continue;
+                const int ri = bj0 / (BN / 2);
+                const int fl = (bj0 & (BN / 2 - 1)) - h * FH + (lane & 15);
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
 #pragma unroll
                     for (int i = 0; i < FM; ++i)
 #pragma unroll
-                        for (int j = 0; j < FN; ++j)
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int k = wr + i * 16 + 4 * (lane >> 4) + v;
-                                const int cl = wc - h * (BN / 2) + j * 16 + (lane & 15);
-                                float val = ldexpf(acc[p][i][j][v], -eu[j]);
-                                if (m == 0 && (cl & 1)) val = 0.f;
-                                st[((cl >> 1) * RS + p + 2 * k) * 2 + (cl & 1)] = val;
-                            }
+                        for (int v = 0; v < 4; ++v) {
+                            const int k = wr + i * 16 + 4 * (lane >> 4) + v;
+                            float val = ldexpf(acc[p][i][j][v], -eu[j]);
+                            if (m == 0 && ri) val = 0.f;
+                            st[(fl * RS + p + 2 * k) * 2 + ri] = val;
+                        }
             }
             __syncthreads();
             const int fbase = col0 / 2 + h * FH;
@@ -1000,8 +1080,11 @@ hipError_t launch_split(const Plan &p, const GemmArgs &a, int bm, int bn, hipStr
     const std::vector<GemmItem> &items = INV ? p.inv_items : p.dir_items;
     const int grid = (int)items.size();
     if (!p.shapes_ok || grid < 1) return hipErrorInvalidValue;
+    // 128 x 128: the direct form takes 64-deep stages (each tile row a whole
+    // 128-byte line of the table; measured 9.9 -> 8.8 ms at TCo1279), the
+    // inverse keeps 32 (64 measured slower)
     if (bm == 128 && bn == 128)
-        k_leg_split<F16, 128, 128, 32, INV, 8><<<grid, 512, 0, s>>>(a);
+        k_leg_split<F16, 128, 128, INV ? 32 : 64, INV, 8><<<grid, 512, 0, s>>>(a);
     else if (bm == 64 && bn == 128)
         k_leg_split<F16, 64, 128, 32, INV, 4><<<grid, 256, 0, s>>>(a);
     else

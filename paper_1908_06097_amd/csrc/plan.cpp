@@ -98,9 +98,9 @@ void gemm_tiles(int prec, int *inv_bm, int *inv_bn, int *dir_bm, int *dir_bn)
     if (prec == SHTX_FP64) {
         *inv_bm = 64; *inv_bn = 64; *dir_bm = 64; *dir_bn = 64;
     } else if (split_form(prec)) {
-        // the autotuner's choices at TCo1279: inverse 128 x 128 (eight waves),
-        // direct 64 x 128 (four waves, two blocks per CU)
-        *inv_bm = 128; *inv_bn = 128; *dir_bm = 64; *dir_bn = 128;
+        // the autotuner's choices at TCo1279: 128 x 128 with eight waves in
+        // both directions (64 x 128, four waves, wins on small workloads)
+        *inv_bm = 128; *inv_bn = 128; *dir_bm = 128; *dir_bn = 128;
     } else {
         *inv_bm = 128; *inv_bn = 128; *dir_bm = 128; *dir_bn = 128;
     }
