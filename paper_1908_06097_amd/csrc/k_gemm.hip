@@ -1074,19 +1074,22 @@ __global__ __launch_bounds__(1024) void k_spec_absmax(const float2 *spec, int64_
     }
 }
 
+// K-stage depth of the split kernels: 128 x 128 direct tiles take 64-deep
+// stages (each tile row of a stage one whole 128-byte line of the table;
+// measured 9.9 -> 8.8 ms at TCo1279), every other shape 32 (64 measured
+// slower for the inverse)
+constexpr int split_stage_depth(bool inverse, int bm) { return (!inverse && bm == 128) ? 64 : 32; }
+
 template <bool F16, bool INV>
 hipError_t launch_split(const Plan &p, const GemmArgs &a, int bm, int bn, hipStream_t s)
 {
     const std::vector<GemmItem> &items = INV ? p.inv_items : p.dir_items;
     const int grid = (int)items.size();
     if (!p.shapes_ok || grid < 1) return hipErrorInvalidValue;
-    // 128 x 128: the direct form takes 64-deep stages (each tile row a whole
-    // 128-byte line of the table; measured 9.9 -> 8.8 ms at TCo1279), the
-    // inverse keeps 32 (64 measured slower)
     if (bm == 128 && bn == 128)
-        k_leg_split<F16, 128, 128, INV ? 32 : 64, INV, 8><<<grid, 512, 0, s>>>(a);
+        k_leg_split<F16, 128, 128, split_stage_depth(INV, 128), INV, 8><<<grid, 512, 0, s>>>(a);
     else if (bm == 64 && bn == 128)
-        k_leg_split<F16, 64, 128, 32, INV, 4><<<grid, 256, 0, s>>>(a);
+        k_leg_split<F16, 64, 128, split_stage_depth(INV, 64), INV, 4><<<grid, 256, 0, s>>>(a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -1121,12 +1124,14 @@ bool gemm_tile_supported(int prec, int bm, int bn)
 
 bool gemm_shapes_ok(const Plan &p)
 {
-    int bk = split_form(p.prec) ? 32 : 16;
+    const bool split = split_form(p.prec);
+    const int bk_inv = split ? split_stage_depth(true, p.inv_bm) : 16;
+    const int bk_dir = split ? split_stage_depth(false, p.dir_bm) : 16;
     if (!gemm_tile_supported(p.prec, p.inv_bm, p.inv_bn) || !gemm_tile_supported(p.prec, p.dir_bm, p.dir_bn))
         return false;
     bool inv_ok = p.inv_items.empty() ||
-                  check_work_list(p, p.inv_items, p.inv_nmain, true, p.inv_bm, p.inv_bn, p.inv_tail_bn, bk);
-    return inv_ok && check_work_list(p, p.dir_items, p.dir_nmain, false, p.dir_bm, p.dir_bn, p.dir_tail_bn, bk);
+                  check_work_list(p, p.inv_items, p.inv_nmain, true, p.inv_bm, p.inv_bn, p.inv_tail_bn, bk_inv);
+    return inv_ok && check_work_list(p, p.dir_items, p.dir_nmain, false, p.dir_bm, p.dir_bn, p.dir_tail_bn, bk_dir);
 }
 
 hipError_t launch_gemm_inverse(const Plan &p, const void *spec, void *four, unsigned *fmax, hipStream_t s)
