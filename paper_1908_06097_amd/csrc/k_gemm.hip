@@ -163,7 +163,7 @@ __device__ inline void inv_epilogue_staged(const GemmArgs &a, const MBlock &b, i
 }
 
 template <typename T, int BM, int BN, int BK, bool INV, int NW = 4>
-__global__ __launch_bounds__(64 * NW, 2) void k_leg_mfma(GemmArgs a)
+__global__ __launch_bounds__(64 * NW, sizeof(T) == 4 ? 4 : 2) void k_leg_mfma(GemmArgs a)
 {
     // NW waves as 2 x (NW / 2): rows split in two, columns in NW / 2
     constexpr int NT = 64 * NW, NWN = NW / 2;
@@ -325,44 +325,63 @@ __global__ __launch_bounds__(64 * NW, 2) void k_leg_mfma(GemmArgs a)
     store(0);
     if (!INV && nstages > 1) meta(BK, mp1, mq1);
     __syncthreads();
-    // a wave whose whole sub-tile lies past the valid rows or columns (the
-    // ragged edge of an m block or of the field range) still loads and
-    // stores its share of the operand tiles but skips the MFMAs, leaving its
-    // SIMD to the other resident block
-    const bool mfma_on = __builtin_amdgcn_readfirstlane(
-        (row0 + wr < (INV ? b.R : b.K0) && col0 + wc < ncol) ? 1 : 0);
-    for (int s = 0; s < nstages; ++s) {
-        const int cur = s & 1;
-        const bool more = s + 1 < nstages;
-        if (more) load((s + 1) * BK);
-        if (!INV && s + 2 < nstages) meta((s + 2) * BK, mp2, mq2);
+    // Row fragments of this wave's sub-tile that hold data: on the ragged
+    // edge of an m block the fragments past the last valid row (and a wave
+    // wholly past the valid rows or columns) skip their LDS reads and MFMAs,
+    // still loading and storing their share of the operand tiles.  The K
+    // loop is instantiated per count so that the accumulators stay in place.
+    const int nfa = __builtin_amdgcn_readfirstlane(
+        col0 + wc < ncol ? min(FM, max(0, ((INV ? b.R : b.K0) - row0 - wr + 15) / 16)) : 0);
+    auto kloop = [&](auto nfa_c) __attribute__((always_inline)) {
+        constexpr int NFA = decltype(nfa_c)::value;
+        for (int s = 0; s < nstages; ++s) {
+            const int cur = s & 1;
+            const bool more = s + 1 < nstages;
+            if (more) load((s + 1) * BK);
+            if (!INV && s + 2 < nstages) meta((s + 2) * BK, mp2, mq2);
+            if constexpr (NFA > 0) {
 #pragma unroll
-        for (int q = 0; q < BK; q += 4) {
-            if (!mfma_on) break;
-            const int qq = q + (lane >> 4);
+                for (int q = 0; q < BK; q += 4) {
+                    const int qq = q + (lane >> 4);
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
-                T av[FM], bv[FN];
+                    for (int p = 0; p < 2; ++p) {
+                        T av[NFA], bv[FN];
 #pragma unroll
-                for (int i = 0; i < FM; ++i) av[i] = As[cur][p][qq][wr + i * 16 + (lane & 15)];
+                        for (int i = 0; i < NFA; ++i) av[i] = As[cur][p][qq][wr + i * 16 + (lane & 15)];
 #pragma unroll
-                for (int j = 0; j < FN; ++j) bv[j] = Bs[cur][p][qq][wc + j * 16 + bcol[q / 4][p]];
+                        for (int j = 0; j < FN; ++j) bv[j] = Bs[cur][p][qq][wc + j * 16 + bcol[q / 4][p]];
 #pragma unroll
-                for (int i = 0; i < FM; ++i)
+                        for (int i = 0; i < NFA; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j) acc[p][i][j] = mfma16x16x4(av[i], bv[j], acc[p][i][j]);
+                            for (int j = 0; j < FN; ++j) acc[p][i][j] = mfma16x16x4(av[i], bv[j], acc[p][i][j]);
+                    }
+                }
             }
-        }
-        if (more) store(cur ^ 1);
-        if (!INV && s + 2 < nstages) {
+            if (more) store(cur ^ 1);
+            if (!INV && s + 2 < nstages) {
 #pragma unroll
-            for (int v = 0; v < NM; ++v) {
-                mp1[v] = mp2[v];
-                mq1[v] = mq2[v];
+                for (int v = 0; v < NM; ++v) {
+                    mp1[v] = mp2[v];
+                    mq1[v] = mq2[v];
+                }
             }
+            __syncthreads();
         }
-        __syncthreads();
-    }
+    };
+    static_assert(FM >= 1 && FM <= 4, "one to four row fragments per wave");
+    // the inverse's ragged rows are few (2 % of its MFMAs against 6 % in the
+    // direct): whole waves only, which keeps its registers within the two
+    // blocks per CU
+    if (nfa == FM || (INV && nfa > 0))
+        kloop(std::integral_constant<int, FM>{});
+    else if (!INV && FM >= 4 && nfa == 3)
+        kloop(std::integral_constant<int, (FM >= 4 ? 3 : 0)>{});
+    else if (!INV && FM >= 3 && nfa == 2)
+        kloop(std::integral_constant<int, (FM >= 3 ? 2 : 0)>{});
+    else if (!INV && FM >= 2 && nfa == 1)
+        kloop(std::integral_constant<int, (FM >= 2 ? 1 : 0)>{});
+    else
+        kloop(std::integral_constant<int, 0>{});
 
     if constexpr (INV && sizeof(T) == 4) {
         static_assert(BM * BN <= NSMEM, "staged inverse tile must fit the operand LDS");
