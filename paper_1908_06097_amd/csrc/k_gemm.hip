@@ -914,7 +914,6 @@ __global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             __syncthreads();
-            // the waves whose columns fall in this half
             // operand column bj is field bj % (BN / 2), real part for
             // bj < BN / 2; fragments of 16 columns never straddle a half
 #pragma unroll
