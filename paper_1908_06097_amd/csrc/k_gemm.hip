@@ -578,11 +578,12 @@ __global__ __launch_bounds__(64 * NW) void k_leg_split(GemmArgs a)
     constexpr int LDK = BK;     // unpadded rows; 16-byte chunks swizzled per row
     constexpr int CH = BK / 8;  // 16-byte chunks per tile row
     static_assert(CH == 4 || CH == 8, "the chunk swizzle permutes four or eight chunks");
-    // physical chunk of logical chunk c in tile row r: c ^ sw(r).  Rows PR
-    // apart share banks (512 bytes); the bits of r / PR go to the swizzle's
-    // upper bits and bit 4 of r to bit 0, so that the MFMA reads (16 rows, two
-    // chunks per 32 lanes) and the direct operand stores (32 rows, one chunk)
-    // meet every bank once
+    // physical chunk of logical chunk c in tile row r: c ^ sw(r), the bits
+    // of r / PR (PR rows span 512 bytes) to the swizzle's upper bits and bit
+    // 4 of r to bit 0.  Measured with an LDS probe: with four chunks (64-byte
+    // rows) the fragment reads run at the rate of linear reads (unswizzled
+    // 64- to 80-byte rows take twice as long); with eight chunks they still
+    // take twice, off the critical path of these kernels
     constexpr int PR = 32 / CH;
     auto sw = [](int r) __attribute__((always_inline)) { return (((r / PR) & (CH / 2 - 1)) << 1) | ((r >> 4) & 1); };
     // LDS row of operand column (field fl, re/im ri): the inverse keeps them
