@@ -18,7 +18,7 @@ Each form is measured in two passes over one plan:
 The forward + adjoint pair (inverse transform, then the adjoint of the
 inverse applied to its grids) is timed the same way as pass 1.
 
-Prints one JSON line (the design doc defines every field).
+Prints one JSON line; main() below assembles its keys.
 """
 import argparse
 import hashlib
@@ -369,8 +369,8 @@ def measure_peaks(torch, shtx):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "see DESIGN.md for how the transform would shard", file=sys.stderr)
+        print(f"bench.py: one GPU only (asked for --gpus {args.gpus}); fields are independent, so "
+              "P GPUs would each transform F/P of them with their own copy of the tables", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -184,7 +184,7 @@ def main():
                          f"LDS instructions per CU-cycle; LDS bank conflicts "
                          f"{m['lds_bank_conflict_cycles_per_cu_cycle']:.3f} cycles per CU-cycle; "
                          f"{m['mfma_insts']:.4g} MFMA and {m['valu_insts']:.4g} VALU instructions\n")
-            fh.write("\nCommands (run from the repository root on the GPU box):\n\n```\n")
+            fh.write("\nCommands (run from the repository root on an MI355X):\n\n```\n")
             fh.write(f"{command}\n```\n")
     path = os.path.join(ROOT, "profiles", "traffic.json")
     recs = []
